@@ -1,0 +1,314 @@
+/*
+ * gf2e_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU reference for dense matrix
+ * multiplication over F_{2^e} = F_2[x]/<f>, 2 <= e <= 10.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load this
+ * library; the GPU product path never calls it and shares no code with it.
+ *
+ * What it follows (M4RIE paper):
+ *   - Section 2 (Notation): an element is a polynomial sum a_i x^i of degree
+ *     < e, identified with the integer sum a_i 2^i; f has degree e and is
+ *     irreducible.  Field multiplication is polynomial multiplication
+ *     followed by reduction modulo f.
+ *   - Section 4, Algorithm 1 (cubic matrix multiplication), read as
+ *     C = A * B with row i of C accumulating A[i][l] * (row l of B) for every
+ *     l: m*l*n field multiplications and as many additions (XOR).
+ *   - The log/antilog-table form of the field product (a generator g, every
+ *     nonzero element is g^i) is the classic table method the paper's
+ *     appendix names for other systems; it is used here only because it is
+ *     fast enough for the larger test sizes.  Every table entry is checked
+ *     against the shift-and-add definition by the test suite.
+ *
+ * Elements are stored one per uint8_t when e <= 8 and one per uint16_t when
+ * e is 9 or 10, row-major with a leading dimension counted in elements.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_EFIELD (-2)
+#define ORC_EINVAL (-1)
+#define ORC_ERANGE (-5)
+
+/* ---------------------------------------------------------------------- */
+/* Polynomials over F_2, held in the bits of an unsigned integer.           */
+/* ---------------------------------------------------------------------- */
+
+static int poly_degree(uint64_t p)
+{
+    int d = -1;
+    while (p) { ++d; p >>= 1; }
+    return d;
+}
+
+/* Remainder of a modulo b (b != 0) in F_2[x]: long division. */
+static uint64_t poly_rem(uint64_t a, uint64_t b)
+{
+    int db = poly_degree(b);
+    for (int d = poly_degree(a); d >= db; d = poly_degree(a))
+        a ^= b << (d - db);
+    return a;
+}
+
+/* Carry-less product a(x)*b(x) in F_2[x]: shift-and-add. */
+static uint64_t poly_mul(uint64_t a, uint64_t b)
+{
+    uint64_t r = 0;
+    for (int i = 0; b >> i; ++i)
+        if ((b >> i) & 1u) r ^= a << i;
+    return r;
+}
+
+/* f is accepted when deg f = e and no polynomial of degree 1..e/2 divides it
+ * (Section 2 asks for an irreducible f). */
+int gf2e_oracle_is_irreducible(int e, uint32_t f)
+{
+    if (e < 1 || e > 16 || poly_degree(f) != e) return 0;
+    for (uint64_t g = 2; poly_degree(g) <= e / 2; ++g)
+        if (poly_rem(f, g) == 0) return 0;
+    return 1;
+}
+
+/* Field product by its definition: multiply as polynomials, reduce mod f. */
+uint32_t gf2e_oracle_mul_def(int e, uint32_t f, uint32_t a, uint32_t b)
+{
+    (void)e;
+    return (uint32_t)poly_rem(poly_mul(a, b), f);
+}
+
+/* Multiplicative order of a nonzero element (0 if a is 0). */
+uint32_t gf2e_oracle_order(int e, uint32_t f, uint32_t a)
+{
+    if (a == 0) return 0;
+    uint32_t x = a, ord = 1;
+    while (x != 1) {
+        x = gf2e_oracle_mul_def(e, f, x, a);
+        if (++ord > (1u << e)) return 0; /* f reducible: no cycle through 1 */
+    }
+    return ord;
+}
+
+/* 1 when x itself generates the multiplicative group (f is primitive). */
+int gf2e_oracle_is_primitive(int e, uint32_t f)
+{
+    if (!gf2e_oracle_is_irreducible(e, f)) return 0;
+    return gf2e_oracle_order(e, f, 2u) == (1u << e) - 1u;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Log / antilog tables.                                                   */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int e;
+    uint32_t f, gen, q;     /* q = 2^e - 1, the group order */
+    uint16_t log[1024];     /* log[0] = 2q: points into the zero tail of exp */
+    uint16_t exp[4 * 1023 + 1];
+} field_tables;
+
+/* Build tables with the smallest generator g found by search (f need not be
+ * primitive).  exp has length 4q+1: exp[i] = g^(i mod q) for i < 2q, zero
+ * from 2q on, so log[a] + log[b] indexes 0 whenever a or b is 0. */
+static int build_tables(int e, uint32_t f, field_tables* T)
+{
+    if (e < 2 || e > 10 || !gf2e_oracle_is_irreducible(e, f)) return ORC_EFIELD;
+    memset(T, 0, sizeof *T);
+    T->e = e; T->f = f; T->q = (1u << e) - 1u;
+    uint32_t g = 2;
+    while (gf2e_oracle_order(e, f, g) != T->q) ++g;
+    T->gen = g;
+    uint32_t x = 1;
+    for (uint32_t i = 0; i < T->q; ++i) {
+        T->exp[i] = (uint16_t)x;
+        T->exp[i + T->q] = (uint16_t)x;
+        T->log[x] = (uint16_t)i;
+        x = gf2e_oracle_mul_def(e, f, x, g);
+    }
+    T->log[0] = (uint16_t)(2 * T->q);
+    return ORC_OK;
+}
+
+static inline uint32_t tab_mul(const field_tables* T, uint32_t a, uint32_t b)
+{
+    return T->exp[T->log[a] + T->log[b]];
+}
+
+/* Exported for the table self-tests: returns the generator used, writes the
+ * q-entry antilog table (exp_out may be NULL). */
+int gf2e_oracle_tables(int e, uint32_t f, uint32_t* gen, uint16_t* exp_out)
+{
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc == ORC_OK) {
+        if (gen) *gen = T->gen;
+        if (exp_out) memcpy(exp_out, T->exp, T->q * sizeof(uint16_t));
+    }
+    free(T);
+    return rc;
+}
+
+/* Table product of two scalars (for the exhaustive table-vs-definition test). */
+int gf2e_oracle_mul_table_all(int e, uint32_t f, uint16_t* out /* 2^e x 2^e */)
+{
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc == ORC_OK) {
+        uint32_t s = 1u << e;
+        for (uint32_t a = 0; a < s; ++a)
+            for (uint32_t b = 0; b < s; ++b)
+                out[a * s + b] = (uint16_t)tab_mul(T, a, b);
+    }
+    free(T);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Matrices.                                                               */
+/* ---------------------------------------------------------------------- */
+
+static inline uint32_t get_el(const void* M, int wide, int64_t idx)
+{
+    return wide ? ((const uint16_t*)M)[idx] : ((const uint8_t*)M)[idx];
+}
+
+static inline void put_el(void* M, int wide, int64_t idx, uint32_t v)
+{
+    if (wide) ((uint16_t*)M)[idx] = (uint16_t)v;
+    else ((uint8_t*)M)[idx] = (uint8_t)v;
+}
+
+/* Rows [row0, row1) of C = A * B by the cubic algorithm (Algorithm 1):
+ * C_i starts at zero and, for every l, receives A[i][l] * B_l.
+ * A is m x k (lda), B is k x n (ldb), C is m x n (ldc).  Rows are split
+ * across nthreads OpenMP threads (nthreads <= 0: the OpenMP default).
+ * Returns ORC_ERANGE if an input entry is not below 2^e. */
+int gf2e_oracle_matmul(int e, uint32_t f, int64_t m, int64_t k, int64_t n,
+                       const void* A, int64_t lda, const void* B, int64_t ldb,
+                       void* C, int64_t ldc, int64_t row0, int64_t row1,
+                       int nthreads)
+{
+    if (m < 0 || k < 0 || n < 0 || row0 < 0 || row1 > m || row0 > row1)
+        return ORC_EINVAL;
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc != ORC_OK) { free(T); return rc; }
+    const int wide = e > 8;
+    const uint32_t lim = 1u << e;
+    int bad = 0;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t i = row0; i < row1; ++i) {
+        uint32_t* acc = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+        for (int64_t l = 0; l < k; ++l) {
+            uint32_t a = get_el(A, wide, i * lda + l);
+            if (a >= lim) { bad = 1; continue; }
+            for (int64_t j = 0; j < n; ++j) {
+                uint32_t b = get_el(B, wide, l * ldb + j);
+                if (b >= lim) { bad = 1; continue; }
+                acc[j] ^= tab_mul(T, a, b);
+            }
+        }
+        for (int64_t j = 0; j < n; ++j) put_el(C, wide, i * ldc + j, acc[j]);
+        free(acc);
+    }
+    free(T);
+    return bad ? ORC_ERANGE : ORC_OK;
+}
+
+/* 1 when every entry of the rows x cols matrix M is below 2^e. */
+static int all_in_field(const void* M, int wide, int64_t rows, int64_t cols, int64_t ld, uint32_t lim)
+{
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t j = 0; j < cols; ++j)
+            if (get_el(M, wide, i * ld + j) >= lim) return 0;
+    return 1;
+}
+
+/* Single entries C[I[s]][J[s]] = sum_l A[I[s]][l] * B[l][J[s]], for checking
+ * large products at sampled positions. */
+int gf2e_oracle_entries(int e, uint32_t f, int64_t m, int64_t k, int64_t n,
+                        const void* A, int64_t lda, const void* B, int64_t ldb,
+                        const int64_t* I, const int64_t* J, int64_t count,
+                        uint32_t* out, int nthreads)
+{
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc != ORC_OK) { free(T); return rc; }
+    const int wide = e > 8;
+    const uint32_t lim = 1u << e;
+    if (!all_in_field(A, wide, m, k, lda, lim) || !all_in_field(B, wide, k, n, ldb, lim)) {
+        free(T);
+        return ORC_ERANGE;
+    }
+    int bad = 0;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(| : bad)
+    for (int64_t s = 0; s < count; ++s) {
+        if (I[s] < 0 || I[s] >= m || J[s] < 0 || J[s] >= n) { bad = 1; continue; }
+        uint32_t acc = 0;
+        for (int64_t l = 0; l < k; ++l)
+            acc ^= tab_mul(T, get_el(A, wide, I[s] * lda + l),
+                           get_el(B, wide, l * ldb + J[s]));
+        out[s] = acc;
+    }
+    free(T);
+    return bad ? ORC_EINVAL : ORC_OK;
+}
+
+/* Freivalds' check of C == A * B over F_{2^e}: with R an n x t matrix of
+ * caller-drawn field elements, compare A * (B * R) with C * R (all products
+ * by the cubic definition).  Returns the number of rows of the m x t result
+ * that differ (0: the check passed), or a negative error code. */
+int64_t gf2e_oracle_freivalds(int e, uint32_t f, int64_t m, int64_t k, int64_t n,
+                              const void* A, int64_t lda, const void* B, int64_t ldb,
+                              const void* C, int64_t ldc, const void* R, int64_t t,
+                              int nthreads)
+{
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc != ORC_OK) { free(T); return rc; }
+    const int wide = e > 8;
+    const uint32_t lim = 1u << e;
+    if (!all_in_field(A, wide, m, k, lda, lim) || !all_in_field(B, wide, k, n, ldb, lim) ||
+        !all_in_field(C, wide, m, n, ldc, lim) || !all_in_field(R, wide, n, t, t, lim)) {
+        free(T);
+        return ORC_ERANGE;
+    }
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+    uint32_t* BR = (uint32_t*)calloc((size_t)(k * t + 1), sizeof(uint32_t));
+    int64_t diff = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t l = 0; l < k; ++l)
+        for (int64_t j = 0; j < n; ++j) {
+            uint32_t b = get_el(B, wide, l * ldb + j);
+            for (int64_t s = 0; s < t; ++s)
+                BR[l * t + s] ^= tab_mul(T, b, get_el(R, wide, j * t + s));
+        }
+#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(+ : diff)
+    for (int64_t i = 0; i < m; ++i) {
+        int row_bad = 0;
+        for (int64_t s = 0; s < t; ++s) {
+            uint32_t lhs = 0, rhs = 0;
+            for (int64_t l = 0; l < k; ++l)
+                lhs ^= tab_mul(T, get_el(A, wide, i * lda + l), BR[l * t + s]);
+            for (int64_t j = 0; j < n; ++j)
+                rhs ^= tab_mul(T, get_el(C, wide, i * ldc + j), get_el(R, wide, j * t + s));
+            if (lhs != rhs) row_bad = 1;
+        }
+        diff += row_bad;
+    }
+    free(BR);
+    free(T);
+    return diff;
+}
+
+int gf2e_oracle_max_threads(void) { return omp_get_max_threads(); }
