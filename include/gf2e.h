@@ -1,0 +1,181 @@
+/*
+ * gf2e.h -- C ABI of the MI355X (gfx950) library for dense matrix
+ * multiplication over F_{2^e}, 2 <= e <= 10.
+ *
+ * What is computed: C = A * B with A m x k and B k x n over
+ * F_{2^e} = F_2[x]/<f> (M4RIE paper, Section 2 for the field and the element
+ * encoding, Section 4 Algorithm 1 for the product).  An element is the
+ * polynomial sum a_i x^i, stored as the integer sum a_i 2^i: one uint8_t per
+ * element when e <= 8, one uint16_t when e is 9 or 10.  f is the full
+ * polynomial with bit e set (x^2+x+1 = 0x7, x^8+x^4+x^3+x^2+1 = 0x11D) and
+ * must be irreducible of degree e.
+ *
+ * How: the Bradshaw-Boothby reduction of Section 5.  Each operand is sliced
+ * into e GF(2) bit-planes (Section 3.2), the Karatsuba schedule forms t(e)
+ * products of plane sums over GF(2) (t = 3, 6, 9, 15, 18, 24, 27, 36, 45 for
+ * e = 2..10), the products are recombined into the 2e-1 coefficients of the
+ * polynomial product, reduced modulo f, and clung back into elements.  Every
+ * step runs as a HIP kernel on the device; the result is exact and unique.
+ *
+ * Conventions for every entry point below:
+ *   - matrix data pointers are DEVICE pointers, row-major, with a leading
+ *     dimension `ld` counted in elements (ld >= cols);
+ *   - the caller owns A, B and C; the library never frees them.  A context
+ *     owns its workspace (bit-planes), tuning cache and graph cache;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - errors are returned as status codes; nothing is thrown or aborted
+ *     across the ABI.  Host-detectable errors are returned before anything is
+ *     enqueued.  Entries >= 2^e are detected on the device and reported by
+ *     the next gf2e_sync (or by the blocking call) as GF2E_ERANGE; the
+ *     offending product's output is then unspecified;
+ *   - C must not overlap A or B (GF2E_EALIAS);
+ *   - m = 0 or n = 0 is a no-op; k = 0 sets C to zero (the empty sum);
+ *   - a context may be used from one host thread at a time.  Calls on one
+ *     context are ordered: a call on a different stream than the previous one
+ *     first waits for that call to finish using the workspace.
+ */
+#ifndef GF2E_H
+#define GF2E_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GF2E_OK = 0,
+    GF2E_EINVAL = -1,  /* null pointer, bad argument */
+    GF2E_EFIELD = -2,  /* e outside 2..10, or f not an irreducible polynomial of degree e */
+    GF2E_ESHAPE = -3,  /* inner/outer dimensions disagree, ld < cols, negative size */
+    GF2E_EALIAS = -4,  /* C overlaps A or B */
+    GF2E_ERANGE = -5,  /* an input entry is >= 2^e (found on the device) */
+    GF2E_ENOMEM = -6,  /* workspace could not be allocated or exceeds the limit */
+    GF2E_EDEVICE = -7, /* a HIP runtime call failed */
+    GF2E_EBUSY = -8    /* serving: request does not fit the memory budget right now */
+};
+
+typedef struct gf2e_ctx gf2e_ctx;
+
+typedef struct {
+    void* data;      /* device pointer to element (0, 0) */
+    int64_t rows;
+    int64_t cols;
+    int64_t ld;      /* elements between the starts of consecutive rows */
+} gf2e_mat;
+
+/* Product-kernel choice (gf2e_config.kernel, gf2e_set_kernel). */
+enum {
+    GF2E_KERNEL_AUTO = -1,        /* autotuned (or planner default) per size bucket */
+    GF2E_KERNEL_MFMA_256 = 0,     /* int8 MFMA, 256x256 tiles */
+    GF2E_KERNEL_MFMA_128 = 1,     /* int8 MFMA, 128x128 tiles */
+    GF2E_KERNEL_MFMA_256x128 = 2, /* int8 MFMA, 256x128 tiles */
+    GF2E_KERNEL_MFMA_64 = 3,      /* int8 MFMA, 64x64 tiles */
+    GF2E_KERNEL_VALU_128 = 4      /* AND/XOR on packed words, 128x128 tiles */
+};
+
+typedef struct {
+    int kernel;              /* GF2E_KERNEL_*; GF2E_KERNEL_AUTO by default */
+    int autotune;            /* 1: time every candidate kernel on first use of a size bucket */
+    int64_t workspace_limit; /* bytes of plane workspace allowed; 0 = no limit */
+} gf2e_config;
+
+/* Context on HIP device `device`.  cfg may be NULL (defaults).  The tuning
+ * cache is read from / written to the file named by GF2E_TUNE_CACHE if set. */
+int gf2e_create(gf2e_ctx** ctx, int device, const gf2e_config* cfg);
+void gf2e_destroy(gf2e_ctx* ctx);
+
+/* C = A * B over F_{2^e} (Section 5 reduction), enqueued on `stream`. */
+int gf2e_mul_async(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
+                   uint32_t f, void* stream);
+
+/* Blocking form: enqueue on the null stream, wait, report device errors. */
+int gf2e_mul(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
+             uint32_t f);
+
+/* Wait for `stream`; return GF2E_ERANGE (once) if any product enqueued since
+ * the previous sync found an entry >= 2^e, else GF2E_OK. */
+int gf2e_sync(gf2e_ctx* ctx, void* stream);
+
+const char* gf2e_strerror(int code);
+
+/* ---- Field and schedule queries (host only; need no GPU) ---------------- */
+
+/* GF2E_OK when 2 <= e <= 10 and f is irreducible of degree e. */
+int gf2e_field_check(int e, uint32_t f);
+
+/* Number t(e) of GF(2) products in the Karatsuba schedule, or < 0. */
+int gf2e_num_products(int e);
+
+/* The schedule of Section 5 for (e, f): product s multiplies
+ * (XOR_{i in u[s]} A_i) by (XOR_{j in v[s]} B_j); coefficient d of the
+ * polynomial product is XOR_{s in w[d]} P_s (d < 2e-1); plane c of the
+ * reduced result is XOR_{s in m[c]} P_s (c < e).  Arrays: u, v of length
+ * >= t, w of length >= 2e-1, m of length >= e; any may be NULL. */
+int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint64_t* w,
+                  uint64_t* m);
+
+/* ---- Stage entry points (the steps of gf2e_mul, for tests and composition).
+ * Plane layouts (64-bit words, bit b of a word = index 64*word + b):
+ *   A-side operand planes: t planes of K64p x Mp words, word (kw, r) = row r,
+ *     k-bits [64kw, 64kw+64);
+ *   B-side operand planes: t planes of K64p x Np words, word (kw, j) =
+ *     column j, k-bits [64kw, 64kw+64);
+ *   product planes: t planes of Mp x (Np/64) words, row-major.
+ * Mp, Np must be multiples of 256 and >= m, n; K64p = 2*ceil(k/128).
+ * All plane pointers are device pointers owned by the caller. */
+
+typedef struct {
+    int t;             /* products */
+    int64_t Mp, Np;    /* padded rows of A-side / B-side planes */
+    int64_t K64p;      /* words along k */
+    int64_t a_bytes, b_bytes, p_bytes; /* sizes of the three plane buffers */
+} gf2e_geometry;
+
+int gf2e_plane_geometry(int e, int64_t m, int64_t k, int64_t n, gf2e_geometry* g);
+
+/* Slice A (m x k) into the t Karatsuba operand planes of the A side
+ * (Section 3.2 slicing fused with the operand sums of Section 5). */
+int gf2e_slice_a(gf2e_ctx* ctx, const gf2e_mat* A, int e, uint64_t* planes, int64_t Mp,
+                 int64_t K64p, void* stream);
+/* Slice B (k x n) column-wise into the t transposed operand planes. */
+int gf2e_slice_b(gf2e_ctx* ctx, const gf2e_mat* B, int e, uint64_t* planes, int64_t Np,
+                 int64_t K64p, void* stream);
+/* P_s = Ahat_s * Bhat_s^T over GF(2) for s < t, one grouped launch of the
+ * given kernel (GF2E_KERNEL_*, AUTO allowed). */
+int gf2e_plane_products(gf2e_ctx* ctx, int kernel, int t, const uint64_t* a_planes,
+                        const uint64_t* b_planes, uint64_t* p_planes, int64_t m, int64_t n,
+                        int64_t Mp, int64_t Np, int64_t K64p, void* stream);
+/* Recombine the t products, reduce modulo f, cling into C (m x n). */
+int gf2e_combine(gf2e_ctx* ctx, int e, uint32_t f, const uint64_t* p_planes, int64_t Mp,
+                 int64_t Np, gf2e_mat* C, void* stream);
+
+/* ---- Kernels, tuning, profiling ----------------------------------------- */
+
+int gf2e_kernel_count(void);
+const char* gf2e_kernel_name(int kernel);
+int gf2e_set_kernel(gf2e_ctx* ctx, int kernel);
+/* Kernel the planner would use now for an (e, m, k, n) product. */
+int gf2e_chosen_kernel(gf2e_ctx* ctx, int e, int64_t m, int64_t k, int64_t n);
+/* Time every candidate kernel for this shape now and cache the fastest. */
+int gf2e_tune(gf2e_ctx* ctx, int e, int64_t m, int64_t k, int64_t n, void* stream);
+
+/* Stage timers: when enabled, every launch of a stage is bracketed by HIP
+ * events on the stream it runs on.  Stages: 0 slice A, 1 slice B,
+ * 2 plane products, 3 combine, 4 batched products (persistent kernel). */
+enum { GF2E_STAGE_SLICE_A = 0, GF2E_STAGE_SLICE_B = 1, GF2E_STAGE_PRODUCTS = 2,
+       GF2E_STAGE_COMBINE = 3, GF2E_STAGE_BATCH_PRODUCTS = 4, GF2E_NUM_STAGES = 5 };
+int gf2e_profile(gf2e_ctx* ctx, int enable);
+/* Waits for the recorded events; total milliseconds and launch count. */
+int gf2e_profile_read(gf2e_ctx* ctx, int stage, double* total_ms, int64_t* launches);
+int gf2e_profile_reset(gf2e_ctx* ctx);
+
+/* Bytes of plane workspace currently held by the context. */
+int64_t gf2e_workspace_bytes(gf2e_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF2E_H */

@@ -1,0 +1,299 @@
+"""Python binding of libgf2e (dense matrix multiplication over F_{2^e} on MI355X).
+
+Argument marshalling only: every step of a product runs in the library's HIP
+kernels (see include/gf2e.h for the C ABI).  PyTorch supplies device memory
+and streams.  If the built library is missing, importing this package still
+works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # loads the HIP runtime the library then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgf2e.so")
+
+OK, EINVAL, EFIELD, ESHAPE, EALIAS, ERANGE, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+KERNEL_AUTO, KERNEL_MFMA_256, KERNEL_MFMA_128, KERNEL_MFMA_256x128, KERNEL_MFMA_64, KERNEL_VALU_128 = \
+    -1, 0, 1, 2, 3, 4
+STAGE_SLICE_A, STAGE_SLICE_B, STAGE_PRODUCTS, STAGE_COMBINE, STAGE_BATCH_PRODUCTS = 0, 1, 2, 3, 4
+
+
+class GF2EError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = strerror(code) if _lib is not None else f"error {code}"
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class Mat(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("ld", ctypes.c_int64)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("workspace_limit", ctypes.c_int64)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int), ("Mp", ctypes.c_int64), ("Np", ctypes.c_int64),
+                ("K64p", ctypes.c_int64), ("a_bytes", ctypes.c_int64), ("b_bytes", ctypes.c_int64),
+                ("p_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+_i32, _i64, _u32, _vp = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
+_P = ctypes.POINTER
+
+# name: (restype, argtypes)
+_SIGS = {
+    "gf2e_create": (_i32, [_P(_vp), _i32, _P(Config)]),
+    "gf2e_destroy": (None, [_vp]),
+    "gf2e_mul": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
+    "gf2e_mul_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
+    "gf2e_sync": (_i32, [_vp, _vp]),
+    "gf2e_strerror": (ctypes.c_char_p, [_i32]),
+    "gf2e_field_check": (_i32, [_i32, _u32]),
+    "gf2e_num_products": (_i32, [_i32]),
+    "gf2e_schedule": (_i32, [_i32, _u32, _P(_i32), _vp, _vp, _vp, _vp]),
+    "gf2e_plane_geometry": (_i32, [_i32, _i64, _i64, _i64, _P(Geometry)]),
+    "gf2e_slice_a": (_i32, [_vp, _P(Mat), _i32, _vp, _i64, _i64, _vp]),
+    "gf2e_slice_b": (_i32, [_vp, _P(Mat), _i32, _vp, _i64, _i64, _vp]),
+    "gf2e_plane_products": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp]),
+    "gf2e_combine": (_i32, [_vp, _i32, _u32, _vp, _i64, _i64, _P(Mat), _vp]),
+    "gf2e_kernel_count": (_i32, []),
+    "gf2e_kernel_name": (ctypes.c_char_p, [_i32]),
+    "gf2e_set_kernel": (_i32, [_vp, _i32]),
+    "gf2e_chosen_kernel": (_i32, [_vp, _i32, _i64, _i64, _i64]),
+    "gf2e_tune": (_i32, [_vp, _i32, _i64, _i64, _i64, _vp]),
+    "gf2e_profile": (_i32, [_vp, _i32]),
+    "gf2e_profile_read": (_i32, [_vp, _i32, _P(ctypes.c_double), _P(_i64)]),
+    "gf2e_profile_reset": (_i32, [_vp]),
+    "gf2e_workspace_bytes": (_i64, [_vp]),
+}
+
+
+def lib():
+    """The loaded libgf2e.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                    "(there is no CPU fallback for the GPU path)")
+            handle = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(handle, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = handle
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().gf2e_strerror(code).decode()
+
+
+def _check(rc: int, what: str = ""):
+    if rc != OK:
+        raise GF2EError(rc, what)
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# Host-only queries
+# ---------------------------------------------------------------------------
+
+def field_check(e: int, f: int) -> bool:
+    return lib().gf2e_field_check(e, f) == OK
+
+
+def num_products(e: int) -> int:
+    rc = lib().gf2e_num_products(e)
+    if rc < 0:
+        raise GF2EError(rc, "num_products")
+    return rc
+
+
+def schedule(e: int, f: int) -> dict:
+    """The Section 5 schedule: u, v (operand subsets), w (polynomial
+    recombination) and m (recombination after reduction mod f)."""
+    t = ctypes.c_int(0)
+    u = (ctypes.c_uint32 * 64)()
+    v = (ctypes.c_uint32 * 64)()
+    w = (ctypes.c_uint64 * 32)()
+    m = (ctypes.c_uint64 * 16)()
+    _check(lib().gf2e_schedule(e, f, ctypes.byref(t), u, v, w, m), "schedule")
+    T = t.value
+    return {"t": T, "u": list(u[:T]), "v": list(v[:T]), "w": list(w[:2 * e - 1]), "m": list(m[:e])}
+
+
+def plane_geometry(e: int, m: int, k: int, n: int) -> Geometry:
+    g = Geometry()
+    _check(lib().gf2e_plane_geometry(e, m, k, n, ctypes.byref(g)), "plane_geometry")
+    return g
+
+
+def kernel_names() -> list:
+    L = lib()
+    return [L.gf2e_kernel_name(i).decode() for i in range(L.gf2e_kernel_count())]
+
+
+# ---------------------------------------------------------------------------
+# Tensors <-> descriptors
+# ---------------------------------------------------------------------------
+
+def elem_dtype(e: int):
+    """torch storage type of one element: uint8 for e <= 8, int16 for 9, 10."""
+    return torch.uint8 if e <= 8 else torch.int16
+
+
+def mat(t: torch.Tensor) -> Mat:
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.numel() > 0 and t.stride(1) != 1:
+        raise ValueError("rows must be contiguous (stride(1) == 1)")
+    ld = t.stride(0) if t.size(0) > 1 else max(t.size(1), 1)
+    return Mat(t.data_ptr() if t.numel() > 0 else None, t.size(0), t.size(1), ld)
+
+
+def _check_elem(t: torch.Tensor, e: int, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not 2 <= e <= 10:
+        return  # the library reports GF2E_EFIELD
+    ok = (t.dtype == torch.uint8) if e <= 8 else (t.dtype in (torch.int16, torch.uint16))
+    if not ok:
+        raise TypeError(f"{name}: elements of F_2^{e} are stored as "
+                        f"{'uint8' if e <= 8 else 'int16/uint16'}, got {t.dtype}")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """Owns a gf2e context (workspace, tuning cache) on one device."""
+
+    def __init__(self, device: int = 0, kernel: int = KERNEL_AUTO, autotune: bool = False,
+                 workspace_limit: int = 0):
+        self.device = device
+        cfg = Config(kernel, 1 if autotune else 0, workspace_limit)
+        h = ctypes.c_void_p()
+        _check(lib().gf2e_create(ctypes.byref(h), device, ctypes.byref(cfg)), "gf2e_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gf2e_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- products ----------------------------------------------------------
+    def mul_async(self, A, B, e: int, f: int, out=None, stream=None):
+        _check_elem(A, e, "A")
+        _check_elem(B, e, "B")
+        if out is None:
+            out = torch.empty((A.size(0), B.size(1)), dtype=A.dtype, device=A.device)
+        _check_elem(out, e, "out")
+        a, b, c = mat(A), mat(B), mat(out)
+        _check(lib().gf2e_mul_async(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                    e, f, _stream_handle(stream)), "gf2e_mul_async")
+        return out
+
+    def sync(self, stream=None):
+        _check(lib().gf2e_sync(self.handle, _stream_handle(stream)), "gf2e_sync")
+
+    def mul(self, A, B, e: int, f: int, out=None, stream=None):
+        out = self.mul_async(A, B, e, f, out=out, stream=stream)
+        self.sync(stream)
+        return out
+
+    # -- stages --------------------------------------------------------------
+    def slice_a(self, A, e, planes, Mp, K64p, stream=None):
+        a = mat(A)
+        _check(lib().gf2e_slice_a(self.handle, ctypes.byref(a), e, ctypes.c_void_p(planes.data_ptr()),
+                                  Mp, K64p, _stream_handle(stream)), "gf2e_slice_a")
+
+    def slice_b(self, B, e, planes, Np, K64p, stream=None):
+        b = mat(B)
+        _check(lib().gf2e_slice_b(self.handle, ctypes.byref(b), e, ctypes.c_void_p(planes.data_ptr()),
+                                  Np, K64p, _stream_handle(stream)), "gf2e_slice_b")
+
+    def plane_products(self, kernel, t, a_planes, b_planes, p_planes, m, n, Mp, Np, K64p,
+                       stream=None):
+        _check(lib().gf2e_plane_products(self.handle, kernel, t, ctypes.c_void_p(a_planes.data_ptr()),
+                                         ctypes.c_void_p(b_planes.data_ptr()),
+                                         ctypes.c_void_p(p_planes.data_ptr()), m, n, Mp, Np, K64p,
+                                         _stream_handle(stream)), "gf2e_plane_products")
+
+    def combine(self, e, f, p_planes, Mp, Np, C, stream=None):
+        c = mat(C)
+        _check(lib().gf2e_combine(self.handle, e, f, ctypes.c_void_p(p_planes.data_ptr()), Mp, Np,
+                                  ctypes.byref(c), _stream_handle(stream)), "gf2e_combine")
+
+    # -- kernels, tuning, timers --------------------------------------------
+    def set_kernel(self, kernel: int):
+        _check(lib().gf2e_set_kernel(self.handle, kernel), "gf2e_set_kernel")
+
+    def chosen_kernel(self, e, m, k, n) -> int:
+        rc = lib().gf2e_chosen_kernel(self.handle, e, m, k, n)
+        if rc < 0:
+            raise GF2EError(rc, "gf2e_chosen_kernel")
+        return rc
+
+    def tune(self, e, m, k, n, stream=None):
+        _check(lib().gf2e_tune(self.handle, e, m, k, n, _stream_handle(stream)), "gf2e_tune")
+
+    def profile(self, enable: bool = True):
+        _check(lib().gf2e_profile(self.handle, 1 if enable else 0), "gf2e_profile")
+
+    def profile_read(self, stage: int):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        _check(lib().gf2e_profile_read(self.handle, stage, ctypes.byref(ms), ctypes.byref(n)),
+               "gf2e_profile_read")
+        return ms.value, n.value
+
+    def profile_reset(self):
+        _check(lib().gf2e_profile_reset(self.handle), "gf2e_profile_reset")
+
+    def workspace_bytes(self) -> int:
+        return int(lib().gf2e_workspace_bytes(self.handle))
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    ctx = _default_ctx.get(device)
+    if ctx is None:
+        ctx = _default_ctx[device] = Context(device)
+    return ctx
+
+
+def mul(A, B, e: int, f: int, out=None, stream=None):
+    """C = A * B over F_2[x]/<f> (blocking; raises on entries >= 2^e)."""
+    return default_context(A.device.index).mul(A, B, e, f, out=out, stream=stream)
+
+
+def mul_async(A, B, e: int, f: int, out=None, stream=None):
+    return default_context(A.device.index).mul_async(A, B, e, f, out=out, stream=stream)

@@ -1,0 +1,92 @@
+// Host-side context of the library (the object behind gf2e_ctx*).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <utility>
+#include <vector>
+
+#include "gf2e.h"
+#include "gf2e_internal.hpp"
+
+namespace gf2e {
+
+struct DeviceGuard {
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    DeviceGuard(const DeviceGuard&) = delete;
+    DeviceGuard& operator=(const DeviceGuard&) = delete;
+
+private:
+    int prev_ = -1;
+};
+
+// Sizes of one product's planes (see the layout notes in gf2e_internal.hpp).
+struct Plan {
+    int e = 0, T = 0;
+    int64_t m = 0, k = 0, n = 0;
+    int64_t Mp = 0, Np = 0, K64p = 0;
+    int64_t a_bytes = 0, b_bytes = 0, p_bytes = 0;
+};
+
+int elem_bytes(int e);
+bool field_ok(int e, uint32_t f);
+int check_mat(const gf2e_mat* M);
+bool overlaps(const gf2e_mat* X, const gf2e_mat* Y, int esz);
+int validate_mul(const gf2e_mat* A, const gf2e_mat* B, const gf2e_mat* C, int e, uint32_t f);
+Plan make_plan(int e, int64_t m, int64_t k, int64_t n);
+int default_kind(int T, int64_t m, int64_t n);
+
+struct BatchGraph;  // defined in batch.hip
+
+struct Ctx {
+    int device = 0;
+    gf2e_config cfg{};
+    int forced_kind = -1;
+    int* d_err = nullptr;  // sticky device flag: an entry >= 2^e was seen
+
+    void* ws = nullptr;  // plane workspace of the plain path
+    int64_t ws_bytes = 0;
+    hipEvent_t ws_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
+
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[GF2E_NUM_STAGES];
+    double prof_ms[GF2E_NUM_STAGES] = {};
+    int64_t prof_n[GF2E_NUM_STAGES] = {};
+    std::vector<hipEvent_t> event_pool;
+
+    std::map<uint64_t, int> tune;  // size bucket -> product kernel
+
+    std::vector<BatchGraph*> batches;  // cached batched graphs (owned)
+
+    hipEvent_t get_event();
+    void order_stream(hipStream_t s);
+    void mark_used(hipStream_t s);
+    int ensure_workspace(int64_t bytes, hipStream_t s);
+    int choose_kind(const Plan& p);
+    int tune_now(const Plan& p, hipStream_t s);
+    void load_tune_cache();
+    void save_tune_entry(uint64_t key, int kind);
+    int run_plan(const Plan& p, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, uint32_t f,
+                 hipStream_t s);
+    void release_batches();
+};
+
+// Brackets one stage launch with HIP events when the context's timers are on.
+class StageTimer {
+public:
+    StageTimer(Ctx* c, int stage, hipStream_t s);
+    ~StageTimer();
+
+private:
+    Ctx* ctx_;
+    int stage_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+}  // namespace gf2e

@@ -1,0 +1,313 @@
+// GF(2) plane products P_s = Ahat_s * Bhat_s^T for all s of a schedule, in
+// one grouped launch (gfx950).  These are the t(e) matrix products over F_2
+// that the Bradshaw-Boothby reduction of Section 5 turns one product over
+// F_{2^e} into.
+//
+// MFMA path: every bit is expanded to a 0/1 byte in LDS and fed to
+// v_mfma_i32_16x16x64_i8; the int32 accumulator holds the exact number of
+// k with A[i][k] = B[k][j] = 1 (exact for k < 2^31), and its low bit is the
+// GF(2) product.  Only the parities are written back, bit-packed.
+//
+// The order of k inside a 64-bit step does not matter for the sum, only that
+// both operands use the same order: A and B chunks are expanded by the same
+// code and read with the same (lane group, byte) -> k assignment.
+//
+// VALU path: the same planes, AND/XOR on 32-bit words (acc ^= a & b, one
+// v_bitop3 per 32 bit-products), parity by popcount at the end.
+#include <hip/hip_runtime.h>
+
+#include "gf2e_internal.hpp"
+
+namespace gf2e {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Expanded chunk c (0..7) of a 128-bit k-step held in two words: 16 bytes,
+// byte (4*q + b) of the chunk = bit (8*b + 4*(c&1) + q) of 32-bit half c>>1.
+__device__ inline uint4 expand_chunk(uint64_t w0, uint64_t w1, int c)
+{
+    const uint64_t w = (c < 4) ? w0 : w1;
+    const uint32_t h = uint32_t(w >> (32 * ((c >> 1) & 1)));
+    const uint32_t s = 4 * (c & 1);
+    const uint32_t M = 0x01010101u;
+    return make_uint4((h >> s) & M, (h >> (s + 1)) & M, (h >> (s + 2)) & M, (h >> (s + 3)) & M);
+}
+
+template <int BM, int BN, int WM, int WN>
+struct MfmaTile {
+    static constexpr int kWavesN = BN / WN;
+    static constexpr int kWaves = (BM / WM) * kWavesN;
+    static constexpr int kThreads = kWaves * 64;
+    static constexpr int FM = WM / 16;
+    static constexpr int FN = WN / 16;
+    static constexpr int kRows = BM + BN;  // staged rows per k-step (A then B)
+    static constexpr int kRowsPerThread = (kRows + kThreads - 1) / kThreads;
+    static_assert(WN % 64 == 0, "a wave must own whole 64-bit output words");
+    static_assert(WM % 16 == 0 && BM % WM == 0 && BN % WN == 0, "tile shape");
+};
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfma_kernel(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
+    int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
+    // Two stages of 8 chunk-major arrays: lds[stage][chunk][row], 16 B each.
+    __shared__ uint4 lds[2][8][TL::kRows];
+
+    const int s = blockIdx.z;
+    const int tile_m = blockIdx.y, tile_n = blockIdx.x;
+    const uint64_t* Ap = Apl + int64_t(s) * K64p * Mp + int64_t(tile_m) * BM;
+    const uint64_t* Bp = Bpl + int64_t(s) * K64p * Np + int64_t(tile_n) * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
+    const int K128 = int(K64p / 2);
+
+    v4i acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+
+    uint64_t stg[RPT][2];
+    auto gload = [&](int kb) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < TL::kRows) {
+                const bool isA = r < BM;
+                const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
+                const int64_t ld = isA ? Mp : Np;
+                stg[q][0] = src[int64_t(2 * kb) * ld];
+                stg[q][1] = src[int64_t(2 * kb + 1) * ld];
+            }
+        }
+    };
+    auto expand_store = [&](int st) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < TL::kRows) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) lds[st][c][r] = expand_chunk(stg[q][0], stg[q][1], c);
+            }
+        }
+    };
+
+    gload(0);
+    expand_store(0);
+    __syncthreads();
+    const int g = lane >> 4, l16 = lane & 15;
+    for (int kb = 0; kb < K128; ++kb) {
+        const int st = kb & 1;
+        const bool more = kb + 1 < K128;
+        if (more) gload(kb + 1);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int c = 4 * kk + g;
+            v4i a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const uint4 x = lds[st][c][wr * WM + 16 * i + l16];
+                a[i] = v4i{int(x.x), int(x.y), int(x.z), int(x.w)};
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const uint4 x = lds[st][c][BM + wc * WN + 16 * j + l16];
+                b[j] = v4i{int(x.x), int(x.y), int(x.z), int(x.w)};
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) expand_store(st ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: lane (g, l16) of block (i, j) holds rows 4g..4g+3, column l16.
+    // The parity ballots of register r give 16 bits of each of 4 rows; lane L
+    // (< 16 * WN/64) assembles row 4*(L&3) + ((L>>2)&3), word L>>4.
+    const int64_t ldp = Np / 64;
+    uint64_t* Ps = P + int64_t(s) * Mp * ldp;
+    const int rg = lane & 3, rr = (lane >> 2) & 3, wsel = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64((acc[i][j][r] & 1) != 0);
+                if (rr == r && wsel == (j >> 2)) word |= ((bal >> (16 * rg)) & 0xFFFFull) << (16 * (j & 3));
+            }
+        if (lane < 16 * (WN / 64)) {
+            const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + 4 * rg + rr;
+            const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + wsel;
+            Ps[row * ldp + colw] = word;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// VALU path: WG tile 128x128, 4 waves of 64x64, thread (ty, tx) of its wave
+// owns rows 8*ty + r and columns tx + 8*c (r, c < 8), so that one ballot per
+// (r, c) yields whole bytes of output words.
+// ---------------------------------------------------------------------------
+constexpr int kValuTile = 128;
+
+__global__ __launch_bounds__(256) void gemm_valu_kernel(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
+    int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
+{
+    // lds[stage][k-dword][row]: 128 A rows then 128 B columns (permuted).
+    __shared__ __align__(16) uint32_t lds[2][4][2 * kValuTile];
+    const int s = blockIdx.z;
+    const int tile_m = blockIdx.y, tile_n = blockIdx.x;
+    const uint64_t* Ap = Apl + int64_t(s) * K64p * Mp + int64_t(tile_m) * kValuTile;
+    const uint64_t* Bp = Bpl + int64_t(s) * K64p * Np + int64_t(tile_n) * kValuTile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int ty = lane >> 3, tx = lane & 7;
+    const int K128 = int(K64p / 2);
+
+    // Staging row of this thread and its LDS slot (B columns permuted so that
+    // column tx + 8c of a 64-column half sits at 8*tx + c).
+    const bool isA = tid < kValuTile;
+    const int srow = isA ? tid : tid - kValuTile;
+    const uint64_t* src = isA ? Ap + srow : Bp + srow;
+    const int64_t ld = isA ? Mp : Np;
+    int slot;
+    if (isA) {
+        slot = srow;
+    } else {
+        const int half = srow >> 6, cc = srow & 63;
+        slot = kValuTile + half * 64 + (cc & 7) * 8 + (cc >> 3);
+    }
+
+    uint32_t acc[8][8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[r][c] = 0;
+
+    uint64_t w0 = src[0], w1 = src[ld];
+    auto store = [&](int st) {
+        lds[st][0][slot] = uint32_t(w0);
+        lds[st][1][slot] = uint32_t(w0 >> 32);
+        lds[st][2][slot] = uint32_t(w1);
+        lds[st][3][slot] = uint32_t(w1 >> 32);
+    };
+    store(0);
+    __syncthreads();
+    for (int kb = 0; kb < K128; ++kb) {
+        const int st = kb & 1;
+        const bool more = kb + 1 < K128;
+        if (more) {
+            w0 = src[int64_t(2 * kb + 2) * ld];
+            w1 = src[int64_t(2 * kb + 3) * ld];
+        }
+#pragma unroll
+        for (int kd = 0; kd < 4; ++kd) {
+            uint32_t a[8], b[8];
+            const uint4* pa = reinterpret_cast<const uint4*>(&lds[st][kd][wr * 64 + ty * 8]);
+            const uint4* pb = reinterpret_cast<const uint4*>(&lds[st][kd][kValuTile + wc * 64 + tx * 8]);
+            const uint4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+            a[0] = a0.x; a[1] = a0.y; a[2] = a0.z; a[3] = a0.w;
+            a[4] = a1.x; a[5] = a1.y; a[6] = a1.z; a[7] = a1.w;
+            b[0] = b0.x; b[1] = b0.y; b[2] = b0.z; b[3] = b0.w;
+            b[4] = b1.x; b[5] = b1.y; b[6] = b1.z; b[7] = b1.w;
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[r][c] ^= a[r] & b[c];
+        }
+        if (more) store(st ^ 1);
+        __syncthreads();
+    }
+
+    const int64_t ldp = Np / 64;
+    uint64_t* Ps = P + int64_t(s) * Mp * ldp;
+    uint64_t word = 0;
+    const int my_ty = lane >> 3, my_r = lane & 7;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint64_t bal = __builtin_amdgcn_ballot_w64((__builtin_popcount(acc[r][c]) & 1) != 0);
+            if (my_r == r) word |= ((bal >> (8 * my_ty)) & 0xFFull) << (8 * c);
+        }
+    const int64_t row = int64_t(tile_m) * kValuTile + wr * 64 + lane;
+    const int64_t colw = (int64_t(tile_n) * kValuTile + wc * 64) / 64;
+    Ps[row * ldp + colw] = word;
+}
+
+template <int BM, int BN, int WM, int WN>
+hipError_t launch_mfma(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P, int64_t m,
+                       int64_t n, int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    const int tm = int(ceil_div(m, BM)), tn = int(ceil_div(n, BN));
+    if (tm * int64_t(BM) > Mp || tn * int64_t(BN) > Np) return hipErrorInvalidValue;
+    dim3 grid(tn, tm, T);
+    hipLaunchKernelGGL((gemm_mfma_kernel<BM, BN, WM, WN>), grid, dim3(TL::kThreads), 0, st, Apl,
+                       Bpl, P, Mp, Np, K64p, tm, tn);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+GemmShape gemm_shape(int kind)
+{
+    switch (kind) {
+        case GEMM_MFMA_256x256: return {256, 256};
+        case GEMM_MFMA_128x128: return {128, 128};
+        case GEMM_MFMA_256x128: return {256, 128};
+        case GEMM_MFMA_64x64: return {64, 64};
+        case GEMM_VALU_128x128: return {kValuTile, kValuTile};
+        default: return {0, 0};
+    }
+}
+
+const char* gemm_name(int kind)
+{
+    switch (kind) {
+        case GEMM_MFMA_256x256: return "mfma_i8_256x256";
+        case GEMM_MFMA_128x128: return "mfma_i8_128x128";
+        case GEMM_MFMA_256x128: return "mfma_i8_256x128";
+        case GEMM_MFMA_64x64: return "mfma_i8_64x64";
+        case GEMM_VALU_128x128: return "valu_xor_128x128";
+        default: return "unknown";
+    }
+}
+
+hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P,
+                       int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
+{
+    if (T <= 0 || m <= 0 || n <= 0 || K64p <= 0) return hipSuccess;
+    if (K64p % 2 != 0) return hipErrorInvalidValue;
+    switch (kind) {
+        case GEMM_MFMA_256x256:
+            return launch_mfma<256, 256, 128, 128>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_MFMA_128x128:
+            return launch_mfma<128, 128, 64, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_MFMA_256x128:
+            return launch_mfma<256, 128, 128, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_MFMA_64x64:
+            return launch_mfma<64, 64, 64, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_VALU_128x128: {
+            const int tm = int(ceil_div(m, kValuTile)), tn = int(ceil_div(n, kValuTile));
+            if (tm * int64_t(kValuTile) > Mp || tn * int64_t(kValuTile) > Np) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(gemm_valu_kernel, dim3(tn, tm, T), dim3(256), 0, st, Apl, Bpl, P, Mp,
+                               Np, K64p, tm, tn);
+            return hipGetLastError();
+        }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gf2e

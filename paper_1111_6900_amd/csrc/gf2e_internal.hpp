@@ -1,0 +1,64 @@
+// Internal interfaces between the host library and the gfx950 kernels.
+//
+// Bit-plane layouts in device memory (all words are uint64_t, bit b of a
+// word is column/index 64*word + b, LSB first):
+//
+//   operand planes (A side):  plane s of T, word (kw, r) at
+//       base + s*K64p*Mp + kw*Mp + r      -- row r of A, k-bits [64kw, 64kw+64)
+//   operand planes (B side):  plane s of T, word (kw, j) at
+//       base + s*K64p*Np + kw*Np + j      -- column j of B, k-bits [64kw, 64kw+64)
+//   product planes:           plane s of T, word (i, w) at
+//       base + s*Mp*ldp + i*ldp + w       -- row i, columns [64w, 64w+64), ldp = Np/64
+//
+// Rows are padded to Mp (Np) and the k dimension to K64p words (a multiple of
+// two, so the product kernels can step 128 bits at a time).  Padding bits are
+// written as zero by the slicing kernels, so padded k contributes nothing.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gf2e {
+
+constexpr int kRowAlign = 256;  // padding of plane rows (largest product tile)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+inline int64_t kwords_padded(int64_t k) { return 2 * ceil_div(k, 128); }
+
+// Product-kernel variants the planner and the autotuner choose among.
+enum GemmKind : int {
+    GEMM_MFMA_256x256 = 0,  // int8 MFMA, 4 waves of 128x128
+    GEMM_MFMA_128x128 = 1,  // int8 MFMA, 4 waves of 64x64
+    GEMM_MFMA_256x128 = 2,  // int8 MFMA, 4 waves of 128x64
+    GEMM_MFMA_64x64 = 3,    // int8 MFMA, 1 wave of 64x64
+    GEMM_VALU_128x128 = 4,  // AND/XOR on packed words, 4 waves of 64x64
+    GEMM_NUM_KINDS = 5
+};
+
+struct GemmShape {
+    int bm, bn;
+};
+GemmShape gemm_shape(int kind);
+const char* gemm_name(int kind);
+
+// Slice rows of A (m x k elements) into T Karatsuba operand planes.
+hipError_t launch_slice_rows(int e, const void* A, int64_t lda, int64_t m, int64_t k,
+                             uint64_t* planes, int64_t Mp, int64_t K64p, int* err,
+                             hipStream_t s);
+// Slice columns of B (k x n elements) into T transposed operand planes.
+hipError_t launch_slice_cols(int e, const void* B, int64_t ldb, int64_t k, int64_t n,
+                             uint64_t* planes, int64_t Np, int64_t K64p, int* err,
+                             hipStream_t s);
+// T plane products P_s = Ahat_s * Bhat_s^T over GF(2), one grouped launch.
+hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P,
+                       int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t K64p,
+                       hipStream_t s);
+// Recombine the T products into 2e-1 coefficient planes, reduce mod f, and
+// write C (m x n elements).
+hipError_t launch_combine(int e, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
+                          int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s);
+// C = 0 (the k = 0 product).
+hipError_t launch_zero(void* C, int64_t rows, int64_t cols, int64_t ld, int elem_bytes,
+                       hipStream_t s);
+
+}  // namespace gf2e

@@ -1,0 +1,157 @@
+"""C-ABI library: loads, exports every declared symbol, host-side logic (no GPU).
+
+The schedule checks pin the Section 5 construction against the plain
+definition of polynomial multiplication and reduction, computed here in
+Python independently of the library.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gf2e.h")
+
+
+def _gf2e():
+    import paper_1111_6900_amd as g
+    try:
+        g.lib()
+    except RuntimeError as exc:  # pragma: no cover - build is part of the suite set-up
+        pytest.skip(str(exc))
+    return g
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf2e_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    g = _gf2e()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(g.lib(), name), name
+
+
+def test_binding_covers_the_header():
+    g = _gf2e()
+    assert set(declared_functions()) <= set(g._SIGS), set(declared_functions()) - set(g._SIGS)
+
+
+def test_strerror_for_every_code():
+    g = _gf2e()
+    codes = [g.OK, g.EINVAL, g.EFIELD, g.ESHAPE, g.EALIAS, g.ERANGE, g.ENOMEM, g.EDEVICE, g.EBUSY]
+    msgs = [g.strerror(c) for c in codes]
+    assert len(set(msgs)) == len(msgs)
+    assert g.strerror(-1234) == "unknown error"
+
+
+def test_field_check():
+    g = _gf2e()
+    for e, f in workload.DEFAULT_POLY.items():
+        assert g.field_check(e, f)
+    assert g.field_check(4, 0x1F)       # irreducible, not primitive
+    assert g.field_check(8, 0x11B)      # AES polynomial
+    for e, f in [(2, 0x5), (4, 0x11), (8, 0x101), (3, 0x13), (1, 0x3), (11, 0x805), (16, 0x1002B)]:
+        assert not g.field_check(e, f), (e, hex(f))
+
+
+def test_field_check_agrees_with_trial_division():
+    from tests import fielddef
+    g = _gf2e()
+    for e in range(2, 11):
+        for f in range(1 << e, 1 << (e + 1)):
+            assert g.field_check(e, f) == fielddef.is_irreducible(e, f), (e, hex(f))
+
+
+def _xpow_mod(d, f, e):
+    r = 1
+    for _ in range(d):
+        r <<= 1
+        if (r >> e) & 1:
+            r ^= f
+    return r
+
+
+EXPECTED_COUNTS = {2: 3, 3: 6, 4: 9, 5: 15, 6: 18, 7: 24, 8: 27, 9: 36, 10: 45}
+
+
+@pytest.mark.parametrize("e,f", sorted(workload.DEFAULT_POLY.items()) + [(4, 0x1F), (8, 0x11B)])
+def test_schedule_tensor_identity(e, f):
+    """Bilinear identity: for all i, j < e,
+    sum_s [i in u_s][j in v_s] x^(coefficients in w) equals x^(i+j), and the
+    reduced map m gives the bits of x^(i+j) mod f."""
+    g = _gf2e()
+    S = g.schedule(e, f)
+    T = S["t"]
+    assert T == EXPECTED_COUNTS[e] == g.num_products(e)
+    for i in range(e):
+        for j in range(e):
+            hits = [s for s in range(T) if (S["u"][s] >> i) & 1 and (S["v"][s] >> j) & 1]
+            for d in range(2 * e - 1):
+                par = sum((S["w"][d] >> s) & 1 for s in hits) & 1
+                assert par == (1 if d == i + j else 0), (i, j, d)
+            red = _xpow_mod(i + j, f, e)
+            for c in range(e):
+                par = sum((S["m"][c] >> s) & 1 for s in hits) & 1
+                assert par == (red >> c) & 1, (i, j, c)
+
+
+def test_schedule_counts_match_table3_best_known():
+    """Table 3 lists 3, 6, 9 and 27 products as the best known for
+    e = 2, 3, 4, 8; the schedule reaches those counts."""
+    g = _gf2e()
+    for e, best in [(2, 3), (3, 6), (4, 9), (8, 27)]:
+        assert g.num_products(e) == best
+    for e in range(5, 11):
+        assert g.num_products(e) < e * e
+
+
+def test_schedule_e2_is_the_section5_formula():
+    """Section 5: C = ((A1+A0)(B1+B0) + A0B0) x + A0B0 + A1B1 modulo x^2+x+1."""
+    g = _gf2e()
+    S = g.schedule(2, 0x7)
+    prods = sorted(zip(S["u"], S["v"]))
+    assert prods == [(1, 1), (2, 2), (3, 3)]
+    idx = {p: s for s, p in enumerate(zip(S["u"], S["v"]))}
+    A0B0, A1B1, MID = idx[(1, 1)], idx[(2, 2)], idx[(3, 3)]
+    assert S["m"][0] == (1 << A0B0) | (1 << A1B1)
+    assert S["m"][1] == (1 << MID) | (1 << A0B0)
+
+
+def test_plane_geometry():
+    g = _gf2e()
+    geo = g.plane_geometry(8, 8192, 8192, 8192)
+    assert (geo.t, geo.Mp, geo.Np, geo.K64p) == (27, 8192, 8192, 128)
+    assert geo.a_bytes == 27 * 128 * 8192 * 8
+    assert geo.p_bytes == 27 * 8192 * 128 * 8
+    geo = g.plane_geometry(2, 1, 1, 1)
+    assert (geo.Mp, geo.Np, geo.K64p) == (256, 256, 2)
+    geo = g.plane_geometry(10, 300, 129, 513)
+    assert (geo.t, geo.Mp, geo.Np, geo.K64p) == (45, 512, 768, 4)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    g = _gf2e()
+    h = ctypes.c_void_p()
+    assert g.lib().gf2e_create(ctypes.byref(h), 0, None) == g.EDEVICE
+    assert not h.value
+
+
+def test_null_context_is_rejected():
+    g = _gf2e()
+    m = g.Mat(None, 0, 0, 0)
+    L = g.lib()
+    assert L.gf2e_mul_async(None, ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), 2, 7, None) == g.EINVAL
+    assert L.gf2e_sync(None, None) == g.EINVAL
+    assert L.gf2e_profile(None, 1) == g.EINVAL
+    assert L.gf2e_workspace_bytes(None) == 0
