@@ -36,6 +36,10 @@ def parse_args():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for rocprofv3: a calibration copy of --copy-mib MiB, then "
+                         "the timed steps only (no CPU, batched or serving legs)")
+    ap.add_argument("--copy-mib", type=int, default=256)
     return ap.parse_args()
 
 
@@ -64,6 +68,121 @@ def cpu_baseline(A, B, e, f, budget_s):
                       f"{spent:.1f} s on {threads} threads"}
 
 
+def batched_leg(g, torch, workload, log, reps=5):
+    """512 mixed products: one graph replay vs 512 plain calls on one stream."""
+    specs = workload.batch_specs(512)
+    mats = workload.batch_inputs(specs)
+    As = [torch.from_numpy(a).to(g.elem_dtype(e)).cuda() for (e, *_), (a, b) in zip(specs, mats)]
+    Bs = [torch.from_numpy(b).to(g.elem_dtype(e)).cuda() for (e, *_), (a, b) in zip(specs, mats)]
+    outs = [torch.empty((a.size(0), b.size(1)), dtype=a.dtype, device="cuda") for a, b in zip(As, Bs)]
+    es = [s[0] for s in specs]
+    fs = [s[1] for s in specs]
+    ctx = g.Context(0)
+
+    def plain():
+        for a, b, o, e, f in zip(As, Bs, outs, es, fs):
+            ctx.mul_async(a, b, e, f, out=o)
+
+    def batched():
+        ctx.mul_batched_async(As, Bs, es, fs, outs=outs)
+
+    def timed(fn):
+        fn()
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    log("batched leg: tuning the tile-class threshold")
+    ctx.tune_batched(As, Bs, es, fs, outs)
+    plain_ms = timed(plain)
+    batched_ms = timed(batched)
+    ctx.sync()
+    info = ctx.batch_info()
+    emacs = sum(m * k * n for (_, _, m, k, n) in specs)
+    bmacs = sum(g.num_products(e) * m * k * n for (e, _, m, k, n) in specs)
+    ctx.close()
+    return {"products": len(specs), "element_macs": emacs, "bit_macs": bmacs,
+            "plain_ms": round(plain_ms, 4), "batched_ms": round(batched_ms, 4),
+            "speedup": round(plain_ms / batched_ms, 3),
+            "batched_element_mac_per_s": emacs / (batched_ms / 1e3),
+            "plain_element_mac_per_s": emacs / (plain_ms / 1e3),
+            "work_items": info["items_large"] + info["items_small"],
+            "tile_threshold": info["threshold"],
+            "plane_arena_bytes": info["arena_bytes"]}
+
+
+def serve_leg(g, torch, workload, log, count=10000, budget=4 << 30, max_inflight=64, load=0.7):
+    """Served requests: n log-uniform in [64, 4096], e ~ U{2..10}.  A closed-loop
+    run (all requests at t=0) gives the saturated rate; an open-loop Poisson
+    run at `load` times that rate gives the latencies."""
+    import numpy as np
+    specs = workload.serve_specs(count)
+    gen = workload.rng(4, 2)
+    nmax = max(n for _, _, n in specs)
+    # Inputs: one device pool per field, each request reads its leading n x n
+    # window (entries are uniform in the field; values do not change the work).
+    pools = {}
+    for e in sorted({e for e, _, _ in specs}):
+        a = workload.field_matrix(gen, nmax, nmax, e)
+        b = workload.field_matrix(gen, nmax, nmax, e)
+        pools[e] = (torch.from_numpy(a).to(g.elem_dtype(e)).cuda(),
+                    torch.from_numpy(b).to(g.elem_dtype(e)).cuda())
+    # Outputs: a distinct region per request.
+    tot = {1: 0, 2: 0}
+    for e, _, n in specs:
+        tot[1 if e <= 8 else 2] += n * n
+    out8 = torch.empty(max(tot[1], 1), dtype=torch.uint8, device="cuda")
+    out16 = torch.empty(max(tot[2], 1), dtype=torch.int16, device="cuda")
+    As, Bs, Cs, es, fs = [], [], [], [], []
+    off = {1: 0, 2: 0}
+    for e, f, n in specs:
+        A, B = pools[e]
+        As.append(A[:n, :n])
+        Bs.append(B[:n, :n])
+        w = 1 if e <= 8 else 2
+        buf = out8 if w == 1 else out16
+        Cs.append(buf[off[w]:off[w] + n * n].view(n, n))
+        off[w] += n * n
+        es.append(e)
+        fs.append(f)
+    emacs = sum(n ** 3 for _, _, n in specs)
+    ctx = g.Context(0)
+    srv = g.Server(ctx, memory_budget=budget, max_inflight=max_inflight)
+    # warm-up on a prefix (first use of every kernel)
+    srv.run_trace(As[:64], Bs[:64], Cs[:64], es[:64], fs[:64], [0.0] * 64)
+    log(f"serving: closed-loop run of {count} requests")
+    t0 = time.perf_counter()
+    closed = srv.run_trace(As, Bs, Cs, es, fs, [0.0] * count)
+    closed_s = time.perf_counter() - t0
+    sat_rate = count / closed_s
+    rate = load * sat_rate
+    arrivals = workload.poisson_arrivals(count, rate)
+    log(f"serving: open-loop Poisson run at {rate:.0f} req/s")
+    t0 = time.perf_counter()
+    opened = srv.run_trace(As, Bs, Cs, es, fs, arrivals)
+    open_s = time.perf_counter() - t0
+    lat = np.array([t["t_done_ns"] for t in opened]) / 1e9 - np.asarray(arrivals)
+    st = srv.stats()
+    srv.close()
+    ctx.close()
+    return {"requests": count, "memory_budget_bytes": budget, "max_inflight": max_inflight,
+            "element_macs": emacs,
+            "saturated_req_per_s": round(sat_rate, 1),
+            "saturated_element_mac_per_s": emacs / closed_s,
+            "offered_req_per_s": round(rate, 1), "load": load,
+            "throughput_req_per_s": round(count / open_s, 1),
+            "throughput_element_mac_per_s": emacs / open_s,
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "max_ms": round(float(lat.max()) * 1e3, 3),
+            "peak_inflight": st["peak_inflight"], "iterations": st["iterations"],
+            "peak_arena_bytes": st["peak_arena_bytes"]}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -84,6 +203,16 @@ def main():
     Ad = torch.from_numpy(A).to(g.elem_dtype(e)).cuda()
     Bd = torch.from_numpy(B).to(g.elem_dtype(e)).cuda()
     C = torch.empty((m, n), dtype=g.elem_dtype(e), device="cuda")
+
+    if args.profile_run:
+        args.no_cpu = args.no_batched = args.no_serve = True
+        # A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the byte counts read for the product kernels.
+        src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = g.Context(0, kernel=args.kernel, autotune=args.kernel < 0)
     stream = torch.cuda.current_stream()
@@ -152,7 +281,7 @@ def main():
     }
 
     # The XOR/popcount VALU kernel on the same product, for comparison.
-    if args.kernel < 0:
+    if args.kernel < 0 and not args.profile_run:
         vctx = g.Context(0, kernel=g.KERNEL_VALU_128)
         vctx.mul_async(Ad, Bd, e, f, out=C)
         vctx.profile(True)
@@ -164,10 +293,10 @@ def main():
         out["valu_products_ms"] = round(ms / max(cnt, 1), 4)
         vctx.close()
 
-    if not args.no_batched and hasattr(g, "batched_bench"):
-        out["batched"] = g.batched_bench(ctx, log=lambda *a: log(args, *a))
-    if not args.no_serve and hasattr(g, "serve_bench"):
-        out["serving"] = g.serve_bench(ctx, log=lambda *a: log(args, *a))
+    if not args.no_batched:
+        out["batched"] = batched_leg(g, torch, workload, lambda *a: log(args, *a))
+    if not args.no_serve:
+        out["serving"] = serve_leg(g, torch, workload, lambda *a: log(args, *a))
 
     if not args.no_cpu:
         log(args, "timing the CPU oracle on a row sample")

@@ -72,7 +72,8 @@ enum {
     GF2E_KERNEL_MFMA_128 = 1,     /* int8 MFMA, 128x128 tiles */
     GF2E_KERNEL_MFMA_256x128 = 2, /* int8 MFMA, 256x128 tiles */
     GF2E_KERNEL_MFMA_64 = 3,      /* int8 MFMA, 64x64 tiles */
-    GF2E_KERNEL_VALU_128 = 4      /* AND/XOR on packed words, 128x128 tiles */
+    GF2E_KERNEL_VALU_128 = 4,     /* AND/XOR on packed words, 128x128 tiles */
+    GF2E_KERNEL_MFMA_256_W8 = 5   /* int8 MFMA, 256x256 tiles, 8 waves of 128x64 */
 };
 
 typedef struct {
@@ -89,6 +90,86 @@ void gf2e_destroy(gf2e_ctx* ctx);
 /* C = A * B over F_{2^e} (Section 5 reduction), enqueued on `stream`. */
 int gf2e_mul_async(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
                    uint32_t f, void* stream);
+
+/* Many independent products C[p] = A[p] * B[p] over F_{2^e[p]} (f[p]), of
+ * any shapes and fields, enqueued on `stream` as one captured HIP graph:
+ * grouped slicing, one persistent grouped launch of all GF(2) plane
+ * products per tile-size class, grouped combining.  After slicing every
+ * product is t(e) GF(2) products of the same shape (Section 5), so one
+ * e-agnostic product kernel serves the whole batch.  A, B, C, e, f are
+ * host arrays of `count` entries; outputs must not overlap any input of
+ * their own product nor each other.  The graph, its plane arena and its
+ * work list are built on the first call with a given set of descriptors
+ * (pointers, shapes, fields) and replayed by later identical calls, which
+ * read the current contents of the same buffers.  Results are bit-identical
+ * to gf2e_mul on each product. */
+int gf2e_mul_batched(gf2e_ctx* ctx, int count, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C,
+                     const int* e, const uint32_t* f, void* stream);
+
+/* Products with min(m, n) >= min_dim take 256x256 tiles in a batch, the rest
+ * 128x128 (default 384). */
+int gf2e_set_batch_threshold(gf2e_ctx* ctx, int64_t min_dim);
+/* Autotune that threshold: build and time the batch for each candidate and
+ * keep the fastest (the batch is computed several times). */
+int gf2e_tune_batched(gf2e_ctx* ctx, int count, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C,
+                      const int* e, const uint32_t* f, void* stream);
+
+typedef struct {
+    int64_t items_large, items_small; /* work items of the last batch, per tile class */
+    int64_t arena_bytes;              /* plane arena of the last batch */
+    int graphs_cached;
+    int64_t graph_builds;
+    int64_t threshold;
+} gf2e_batch_stats;
+int gf2e_batch_info(gf2e_ctx* ctx, gf2e_batch_stats* out);
+
+/* ---- Serving ------------------------------------------------------------
+ * A request loop with continuous batching.  A scheduler thread admits
+ * submitted products in arrival order while their bit-plane footprint fits
+ * `memory_budget` bytes of device memory and a descriptor slot is free,
+ * slices them into planes that stay resident until the request completes,
+ * and runs iterations of the persistent plane-product kernel over the tiles
+ * of every admitted request (at most `quantum_macs` bit-MACs per iteration),
+ * so requests that arrive while others are on the GPU share its launches.
+ * Results are identical to gf2e_mul of the same product.  A, B, C passed to
+ * submit must stay valid and untouched until the request is waited for. */
+typedef struct gf2e_server gf2e_server;
+
+typedef struct {
+    int64_t memory_budget;           /* device bytes for resident planes (admission limit) */
+    int max_inflight;                /* admitted requests at once (1..4096) */
+    int64_t quantum_macs;            /* plane-product bit-MACs per iteration; 0 = no limit */
+    int64_t max_items_per_iteration; /* tile items per iteration; 0 = 262144 */
+} gf2e_server_config;
+
+typedef struct {
+    int64_t t_submit_ns; /* times since the server (or run_trace call) started */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;   /* when the scheduler saw the completion event */
+    int status;          /* GF2E_OK, GF2E_ERANGE, ... */
+} gf2e_req_times;
+
+typedef struct {
+    int64_t completed, iterations, element_macs, peak_arena_bytes;
+    int peak_inflight;
+} gf2e_server_counters;
+
+int gf2e_server_create(gf2e_ctx* ctx, const gf2e_server_config* cfg, gf2e_server** out);
+/* Drains every submitted request, then frees the server. */
+void gf2e_server_destroy(gf2e_server* srv);
+/* Validates and queues a request (never blocks).  GF2E_EBUSY: its footprint
+ * exceeds the whole budget, so it could never be admitted. */
+int gf2e_server_submit(gf2e_server* srv, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
+                       uint32_t f, uint64_t* ticket);
+int gf2e_server_poll(gf2e_server* srv, uint64_t ticket, int* done, gf2e_req_times* times);
+/* Blocks until the request is done; returns its status and forgets it. */
+int gf2e_server_wait(gf2e_server* srv, uint64_t ticket, gf2e_req_times* times);
+int gf2e_server_stats(gf2e_server* srv, gf2e_server_counters* out);
+/* Open-loop driver: submits request i at arrival_s[i] seconds after the call
+ * starts, then waits for all; out[i] gets times relative to that start. */
+int gf2e_server_run_trace(gf2e_server* srv, int count, const gf2e_mat* A, const gf2e_mat* B,
+                          gf2e_mat* C, const int* e, const uint32_t* f, const double* arrival_s,
+                          gf2e_req_times* out);
 
 /* Blocking form: enqueue on the null stream, wait, report device errors. */
 int gf2e_mul(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
@@ -163,9 +244,9 @@ int gf2e_tune(gf2e_ctx* ctx, int e, int64_t m, int64_t k, int64_t n, void* strea
 
 /* Stage timers: when enabled, every launch of a stage is bracketed by HIP
  * events on the stream it runs on.  Stages: 0 slice A, 1 slice B,
- * 2 plane products, 3 combine, 4 batched products (persistent kernel). */
+ * 2 plane products, 3 combine, 4 a whole batched graph. */
 enum { GF2E_STAGE_SLICE_A = 0, GF2E_STAGE_SLICE_B = 1, GF2E_STAGE_PRODUCTS = 2,
-       GF2E_STAGE_COMBINE = 3, GF2E_STAGE_BATCH_PRODUCTS = 4, GF2E_NUM_STAGES = 5 };
+       GF2E_STAGE_COMBINE = 3, GF2E_STAGE_BATCH = 4, GF2E_NUM_STAGES = 5 };
 int gf2e_profile(gf2e_ctx* ctx, int enable);
 /* Waits for the recorded events; total milliseconds and launch count. */
 int gf2e_profile_read(gf2e_ctx* ctx, int stage, double* total_ms, int64_t* launches);

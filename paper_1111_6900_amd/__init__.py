@@ -17,9 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgf2e.so")
 
 OK, EINVAL, EFIELD, ESHAPE, EALIAS, ERANGE, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
-KERNEL_AUTO, KERNEL_MFMA_256, KERNEL_MFMA_128, KERNEL_MFMA_256x128, KERNEL_MFMA_64, KERNEL_VALU_128 = \
-    -1, 0, 1, 2, 3, 4
-STAGE_SLICE_A, STAGE_SLICE_B, STAGE_PRODUCTS, STAGE_COMBINE, STAGE_BATCH_PRODUCTS = 0, 1, 2, 3, 4
+KERNEL_AUTO, KERNEL_MFMA_256, KERNEL_MFMA_128, KERNEL_MFMA_256x128, KERNEL_MFMA_64, KERNEL_VALU_128, \
+    KERNEL_MFMA_256_W8 = -1, 0, 1, 2, 3, 4, 5
+STAGE_SLICE_A, STAGE_SLICE_B, STAGE_PRODUCTS, STAGE_COMBINE, STAGE_BATCH = 0, 1, 2, 3, 4
 
 
 class GF2EError(RuntimeError):
@@ -45,6 +45,28 @@ class Geometry(ctypes.Structure):
                 ("p_bytes", ctypes.c_int64)]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("items_large", ctypes.c_int64), ("items_small", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("graphs_cached", ctypes.c_int),
+                ("graph_builds", ctypes.c_int64), ("threshold", ctypes.c_int64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_int64), ("max_inflight", ctypes.c_int),
+                ("quantum_macs", ctypes.c_int64), ("max_items_per_iteration", ctypes.c_int64)]
+
+
+class ReqTimes(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64), ("status", ctypes.c_int)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("element_macs", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_int64),
+                ("peak_inflight", ctypes.c_int)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -58,6 +80,17 @@ _SIGS = {
     "gf2e_mul": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
     "gf2e_mul_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
     "gf2e_sync": (_i32, [_vp, _vp]),
+    "gf2e_mul_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gf2e_set_batch_threshold": (_i32, [_vp, _i64]),
+    "gf2e_tune_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gf2e_batch_info": (_i32, [_vp, _P(BatchStats)]),
+    "gf2e_server_create": (_i32, [_vp, _P(ServerConfig), _P(_vp)]),
+    "gf2e_server_destroy": (None, [_vp]),
+    "gf2e_server_submit": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _P(ctypes.c_uint64)]),
+    "gf2e_server_poll": (_i32, [_vp, ctypes.c_uint64, _P(_i32), _P(ReqTimes)]),
+    "gf2e_server_wait": (_i32, [_vp, ctypes.c_uint64, _P(ReqTimes)]),
+    "gf2e_server_stats": (_i32, [_vp, _P(ServerCounters)]),
+    "gf2e_server_run_trace": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_strerror": (ctypes.c_char_p, [_i32]),
     "gf2e_field_check": (_i32, [_i32, _u32]),
     "gf2e_num_products": (_i32, [_i32]),
@@ -225,6 +258,50 @@ class Context:
         self.sync(stream)
         return out
 
+    # -- batched -------------------------------------------------------------
+    def _batch_args(self, As, Bs, Cs, es, fs):
+        n = len(As)
+        if not (len(Bs) == len(Cs) == len(es) == len(fs) == n):
+            raise ValueError("batch lists differ in length")
+        for i in range(n):
+            _check_elem(As[i], es[i], f"A[{i}]")
+            _check_elem(Bs[i], es[i], f"B[{i}]")
+            _check_elem(Cs[i], es[i], f"C[{i}]")
+        MA = (Mat * max(n, 1))(*[mat(t) for t in As])
+        MB = (Mat * max(n, 1))(*[mat(t) for t in Bs])
+        MC = (Mat * max(n, 1))(*[mat(t) for t in Cs])
+        E = (ctypes.c_int * max(n, 1))(*es)
+        F = (ctypes.c_uint32 * max(n, 1))(*fs)
+        return n, MA, MB, MC, E, F
+
+    def mul_batched_async(self, As, Bs, es, fs, outs=None, stream=None):
+        """C[p] = A[p] * B[p] over F_2^e[p] for every p: one graph launch."""
+        if outs is None:
+            outs = [torch.empty((a.size(0), b.size(1)), dtype=a.dtype, device=a.device)
+                    for a, b in zip(As, Bs)]
+        n, MA, MB, MC, E, F = self._batch_args(As, Bs, outs, es, fs)
+        _check(lib().gf2e_mul_batched(self.handle, n, MA, MB, MC, E, F, _stream_handle(stream)),
+               "gf2e_mul_batched")
+        return outs
+
+    def mul_batched(self, As, Bs, es, fs, outs=None, stream=None):
+        outs = self.mul_batched_async(As, Bs, es, fs, outs=outs, stream=stream)
+        self.sync(stream)
+        return outs
+
+    def tune_batched(self, As, Bs, es, fs, outs, stream=None):
+        n, MA, MB, MC, E, F = self._batch_args(As, Bs, outs, es, fs)
+        _check(lib().gf2e_tune_batched(self.handle, n, MA, MB, MC, E, F, _stream_handle(stream)),
+               "gf2e_tune_batched")
+
+    def set_batch_threshold(self, min_dim: int):
+        _check(lib().gf2e_set_batch_threshold(self.handle, min_dim), "gf2e_set_batch_threshold")
+
+    def batch_info(self) -> dict:
+        st = BatchStats()
+        _check(lib().gf2e_batch_info(self.handle, ctypes.byref(st)), "gf2e_batch_info")
+        return {k: getattr(st, k) for k, _ in BatchStats._fields_}
+
     # -- stages --------------------------------------------------------------
     def slice_a(self, A, e, planes, Mp, K64p, stream=None):
         a = mat(A)
@@ -297,3 +374,68 @@ def mul(A, B, e: int, f: int, out=None, stream=None):
 
 def mul_async(A, B, e: int, f: int, out=None, stream=None):
     return default_context(A.device.index).mul_async(A, B, e, f, out=out, stream=stream)
+
+
+class Server:
+    """Continuous-batching request loop (see gf2e_server_* in include/gf2e.h)."""
+
+    def __init__(self, ctx: Context, memory_budget: int = 4 << 30, max_inflight: int = 64,
+                 quantum_macs: int = 1 << 40, max_items_per_iteration: int = 0):
+        self.ctx = ctx
+        cfg = ServerConfig(memory_budget, max_inflight, quantum_macs, max_items_per_iteration)
+        h = ctypes.c_void_p()
+        _check(lib().gf2e_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)),
+               "gf2e_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gf2e_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, A, B, e: int, f: int, out=None) -> int:
+        _check_elem(A, e, "A")
+        _check_elem(B, e, "B")
+        if out is None:
+            out = torch.empty((A.size(0), B.size(1)), dtype=A.dtype, device=A.device)
+        t = ctypes.c_uint64(0)
+        a, b, c = mat(A), mat(B), mat(out)
+        _check(lib().gf2e_server_submit(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                        e, f, ctypes.byref(t)), "gf2e_server_submit")
+        self._keep[t.value] = (A, B, out)  # tensors stay alive until waited for
+        return t.value
+
+    def wait(self, ticket: int):
+        """(output tensor, times dict); raises on a failed request."""
+        tm = ReqTimes()
+        rc = lib().gf2e_server_wait(self.handle, ticket, ctypes.byref(tm))
+        A, B, out = self._keep.pop(ticket, (None, None, None))
+        _check(rc, "gf2e_server_wait")
+        return out, {k: getattr(tm, k) for k, _ in ReqTimes._fields_}
+
+    def stats(self) -> dict:
+        st = ServerCounters()
+        _check(lib().gf2e_server_stats(self.handle, ctypes.byref(st)), "gf2e_server_stats")
+        return {k: getattr(st, k) for k, _ in ServerCounters._fields_}
+
+    def run_trace(self, As, Bs, Cs, es, fs, arrival_s):
+        """Open-loop run: request i submitted at arrival_s[i] s; per-request times."""
+        n = len(As)
+        MA = (Mat * max(n, 1))(*[mat(t) for t in As])
+        MB = (Mat * max(n, 1))(*[mat(t) for t in Bs])
+        MC = (Mat * max(n, 1))(*[mat(t) for t in Cs])
+        E = (ctypes.c_int * max(n, 1))(*es)
+        F = (ctypes.c_uint32 * max(n, 1))(*fs)
+        T = (ctypes.c_double * max(n, 1))(*[float(x) for x in arrival_s])
+        out = (ReqTimes * max(n, 1))()
+        rc = lib().gf2e_server_run_trace(self.handle, n, MA, MB, MC, E, F, T, out)
+        _check(rc, "gf2e_server_run_trace")
+        return [{k: getattr(out[i], k) for k, _ in ReqTimes._fields_} for i in range(n)]

@@ -1,16 +1,316 @@
-// Batched products (filled in by the batching runtime).
+// Batched products: many independent C_p = A_p * B_p over F_{2^e_p} of
+// uneven shapes and mixed e in three launches, captured once into a HIP
+// graph and replayed.
+//
+// After slicing, a product over any F_{2^e} is t(e) GF(2) plane products of
+// the same (m, n, k) (Section 5), so one persistent grouped kernel serves
+// every field: its work list holds (product, plane, tile) items, sorted by
+// decreasing k so the longest tiles start first, and workgroups take items
+// from a global counter until the list is exhausted.  Slicing and combining
+// run as one grouped launch each, dispatching on e per product.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <vector>
 
 #include "ctx.hpp"
 
 namespace gf2e {
 
-struct BatchGraph {};
+struct BatchGraph {
+    std::vector<uint8_t> key;
+    int count = 0;
+    void* arena = nullptr;
+    int64_t arena_bytes = 0;
+    BatchProduct* d_prods = nullptr;
+    WorkItem* d_items = nullptr;
+    int* d_counters = nullptr;
+    int n_items[2] = {0, 0};
+    int grid[2] = {0, 0};
+    int max_slice_blocks = 0, max_combine_blocks = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~BatchGraph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (d_counters) (void)hipFree(d_counters);
+        if (d_items) (void)hipFree(d_items);
+        if (d_prods) (void)hipFree(d_prods);
+        if (arena) (void)hipFree(arena);
+    }
+};
+
+namespace {
+
+constexpr int kMaxCachedBatches = 8;
+constexpr int kClassKinds[2] = {GEMM_MFMA_256x256_W8, GEMM_MFMA_128x128};
+
+template <class T>
+void put(std::vector<uint8_t>& key, const T& v)
+{
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+    key.insert(key.end(), p, p + sizeof(T));
+}
+
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
 
 void Ctx::release_batches()
 {
+    if (!batches.empty()) (void)hipDeviceSynchronize();
     for (BatchGraph* b : batches) delete b;
     batches.clear();
 }
 
+static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C,
+                       const int* e, const uint32_t* f, std::vector<uint8_t>&& key, BatchGraph** out)
+{
+    auto bg = std::make_unique<BatchGraph>();
+    bg->key = std::move(key);
+    const int TPB = batch_threads_per_block();
+
+    // Plans and the arena layout.
+    std::vector<BatchProduct> prods;
+    std::vector<int64_t> offs;
+    int64_t total = 0;
+    for (int p = 0; p < count; ++p) {
+        const int64_t m = A[p].rows, k = A[p].cols, n = B[p].cols;
+        if (m == 0 || n == 0) continue;
+        const Plan pl = make_plan(e[p], m, k, n);
+        BatchProduct d{};
+        d.A = A[p].data; d.B = B[p].data; d.C = C[p].data;
+        d.lda = A[p].ld; d.ldb = B[p].ld; d.ldc = C[p].ld;
+        d.m = m; d.k = k; d.n = n;
+        d.Mp = pl.Mp; d.Np = pl.Np; d.K64p = pl.K64p;
+        d.e = e[p]; d.T = pl.T; d.f = f[p];
+        d.slice_a_blocks = k > 0 ? int32_t(pl.Mp / TPB * pl.K64p) : 0;
+        d.slice_b_blocks = k > 0 ? int32_t(pl.Np / TPB * pl.K64p) : 0;
+        d.combine_blocks = int32_t(ceil_div(m * ceil_div(n, 64), TPB));
+        offs.push_back(total);
+        if (k > 0) total += align256(pl.a_bytes) + align256(pl.b_bytes) + align256(pl.p_bytes);
+        prods.push_back(d);
+        bg->max_slice_blocks = std::max(bg->max_slice_blocks, d.slice_a_blocks + d.slice_b_blocks);
+        bg->max_combine_blocks = std::max(bg->max_combine_blocks, d.combine_blocks);
+    }
+    bg->count = int(prods.size());
+    if (bg->count > 65535) return GF2E_EINVAL;
+    if (total > 0 && hipMalloc(&bg->arena, size_t(total)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GF2E_ENOMEM;
+    }
+    bg->arena_bytes = total;
+    for (size_t i = 0; i < prods.size(); ++i) {
+        BatchProduct& d = prods[i];
+        if (d.k == 0) continue;
+        uint8_t* base = static_cast<uint8_t*>(bg->arena) + offs[i];
+        const Plan pl = make_plan(d.e, d.m, d.k, d.n);
+        d.Apl = reinterpret_cast<uint64_t*>(base);
+        d.Bpl = reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes));
+        d.P = reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes) + align256(pl.b_bytes));
+    }
+
+    // Work lists: size class by the smaller output dimension.
+    std::vector<WorkItem> items[2];
+    for (size_t i = 0; i < prods.size(); ++i) {
+        const BatchProduct& d = prods[i];
+        if (d.k == 0) continue;
+        const int cls = std::min(d.m, d.n) >= c->batch_threshold ? 0 : 1;
+        const GemmShape sh = gemm_shape(kClassKinds[cls]);
+        const int tm = int(ceil_div(d.m, sh.bm)), tn = int(ceil_div(d.n, sh.bn));
+        for (int s = 0; s < d.T; ++s)
+            for (int a = 0; a < tm; ++a)
+                for (int b = 0; b < tn; ++b) items[cls].push_back({int32_t(i), s, a, b});
+    }
+    const char* shuffle = std::getenv("GF2E_BATCH_SHUFFLE");
+    for (int cls = 0; cls < 2; ++cls) {
+        auto& v = items[cls];
+        if (shuffle && *shuffle) {
+            std::mt19937_64 rng(std::strtoull(shuffle, nullptr, 10));
+            std::shuffle(v.begin(), v.end(), rng);
+        } else {
+            std::stable_sort(v.begin(), v.end(), [&](const WorkItem& x, const WorkItem& y) {
+                return prods[x.prod].K64p > prods[y.prod].K64p;
+            });
+        }
+        bg->n_items[cls] = int(v.size());
+        bg->grid[cls] = v.empty() ? 0 : persistent_grid(kClassKinds[cls]);
+        if (!v.empty() && bg->grid[cls] <= 0) return GF2E_EDEVICE;
+    }
+
+    // Device copies of the descriptors and work lists.
+    const size_t nall = items[0].size() + items[1].size();
+    if (hipMalloc(&bg->d_prods, sizeof(BatchProduct) * std::max<size_t>(prods.size(), 1)) != hipSuccess ||
+        hipMalloc(&bg->d_items, sizeof(WorkItem) * std::max<size_t>(nall, 1)) != hipSuccess ||
+        hipMalloc(&bg->d_counters, 2 * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GF2E_ENOMEM;
+    }
+    if ((!prods.empty() && hipMemcpy(bg->d_prods, prods.data(), sizeof(BatchProduct) * prods.size(),
+                                     hipMemcpyHostToDevice) != hipSuccess) ||
+        (!items[0].empty() && hipMemcpy(bg->d_items, items[0].data(), sizeof(WorkItem) * items[0].size(),
+                                        hipMemcpyHostToDevice) != hipSuccess) ||
+        (!items[1].empty() && hipMemcpy(bg->d_items + items[0].size(), items[1].data(),
+                                        sizeof(WorkItem) * items[1].size(), hipMemcpyHostToDevice) != hipSuccess))
+        return GF2E_EDEVICE;
+
+    // Capture: reset counters, grouped slicing, the persistent products of
+    // each size class, grouped combining.
+    if (hipStreamCreateWithFlags(&bg->cap, hipStreamNonBlocking) != hipSuccess) return GF2E_EDEVICE;
+    if (hipStreamBeginCapture(bg->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return GF2E_EDEVICE;
+    hipError_t err = launch_reset_counters(bg->d_counters, 2, bg->cap);
+    if (err == hipSuccess)
+        err = launch_batched_slice(bg->d_prods, bg->count, bg->max_slice_blocks, c->d_err, bg->cap);
+    for (int cls = 0; cls < 2 && err == hipSuccess; ++cls)
+        err = launch_persistent_gemm(kClassKinds[cls], bg->d_prods,
+                                     bg->d_items + (cls ? items[0].size() : 0), bg->n_items[cls],
+                                     bg->d_counters + cls, bg->grid[cls], bg->cap);
+    if (err == hipSuccess)
+        err = launch_batched_combine(bg->d_prods, bg->count, bg->max_combine_blocks, bg->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t end = hipStreamEndCapture(bg->cap, &graph);
+    bg->graph = graph;
+    if (err != hipSuccess || end != hipSuccess || !graph) return GF2E_EDEVICE;
+    if (hipGraphInstantiate(&bg->exec, bg->graph, nullptr, nullptr, 0) != hipSuccess) return GF2E_EDEVICE;
+    *out = bg.release();
+    return GF2E_OK;
+}
+
 }  // namespace gf2e
+
+using namespace gf2e;
+
+extern "C" {
+
+int gf2e_mul_batched(gf2e_ctx* handle, int count, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C,
+                     const int* e, const uint32_t* f, void* stream)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c || count < 0) return GF2E_EINVAL;
+    if (count == 0) return GF2E_OK;
+    if (!A || !B || !C || !e || !f) return GF2E_EINVAL;
+    for (int p = 0; p < count; ++p) {
+        int rc = validate_mul(&A[p], &B[p], &C[p], e[p], f[p]);
+        if (rc) return rc;
+    }
+    // Outputs must not overlap each other either: sort their byte ranges by
+    // start and compare each start with the furthest end seen so far.
+    {
+        std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+        for (int p = 0; p < count; ++p) {
+            if (C[p].rows <= 0 || C[p].cols <= 0) continue;
+            const uintptr_t lo = reinterpret_cast<uintptr_t>(C[p].data);
+            ranges.push_back(
+                {lo, lo + uintptr_t(((C[p].rows - 1) * C[p].ld + C[p].cols) * elem_bytes(e[p]))});
+        }
+        std::sort(ranges.begin(), ranges.end());
+        uintptr_t end = 0;
+        for (size_t i = 0; i < ranges.size(); ++i) {
+            if (i > 0 && ranges[i].first < end) return GF2E_EALIAS;
+            end = std::max(end, ranges[i].second);
+        }
+    }
+    std::vector<uint8_t> key;
+    put(key, c->batch_threshold);
+    put(key, count);
+    for (int p = 0; p < count; ++p) {
+        put(key, A[p]); put(key, B[p]); put(key, C[p]); put(key, e[p]); put(key, f[p]);
+    }
+    if (const char* sh = std::getenv("GF2E_BATCH_SHUFFLE")) key.insert(key.end(), sh, sh + std::strlen(sh));
+
+    DeviceGuard guard(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchGraph* bg = nullptr;
+    for (size_t i = 0; i < c->batches.size(); ++i)
+        if (c->batches[i]->key == key) {
+            bg = c->batches[i];
+            // most recently used goes last
+            c->batches.erase(c->batches.begin() + long(i));
+            c->batches.push_back(bg);
+            break;
+        }
+    if (!bg) {
+        if (int(c->batches.size()) >= kMaxCachedBatches) {
+            (void)hipDeviceSynchronize();
+            delete c->batches.front();
+            c->batches.erase(c->batches.begin());
+        }
+        int rc = build_batch(c, count, A, B, C, e, f, std::move(key), &bg);
+        if (rc) return rc;
+        c->batches.push_back(bg);
+        c->batch_builds += 1;
+    }
+    c->order_stream(s);
+    hipError_t err;
+    {
+        StageTimer t(c, GF2E_STAGE_BATCH, s);
+        err = hipGraphLaunch(bg->exec, s);
+    }
+    c->mark_used(s);
+    c->last_batch_items[0] = bg->n_items[0];
+    c->last_batch_items[1] = bg->n_items[1];
+    c->last_batch_arena = bg->arena_bytes;
+    return err == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+}
+
+int gf2e_set_batch_threshold(gf2e_ctx* handle, int64_t min_dim)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c || min_dim < 0) return GF2E_EINVAL;
+    c->batch_threshold = min_dim;
+    return GF2E_OK;
+}
+
+int gf2e_batch_info(gf2e_ctx* handle, gf2e_batch_stats* out)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c || !out) return GF2E_EINVAL;
+    out->items_large = c->last_batch_items[0];
+    out->items_small = c->last_batch_items[1];
+    out->arena_bytes = c->last_batch_arena;
+    out->graphs_cached = int(c->batches.size());
+    out->graph_builds = c->batch_builds;
+    out->threshold = c->batch_threshold;
+    return GF2E_OK;
+}
+
+int gf2e_tune_batched(gf2e_ctx* handle, int count, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C,
+                      const int* e, const uint32_t* f, void* stream)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c) return GF2E_EINVAL;
+    static const int64_t candidates[] = {0, 256, 384, 512, 768, INT64_MAX};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard guard(c->device);
+    hipEvent_t e0 = c->get_event(), e1 = c->get_event();
+    if (!e0 || !e1) return GF2E_EDEVICE;
+    int64_t best = c->batch_threshold;
+    float best_ms = -1;
+    for (int64_t th : candidates) {
+        c->batch_threshold = th;
+        int rc = gf2e_mul_batched(handle, count, A, B, C, e, f, stream);  // build + warm-up
+        if (rc) { c->batch_threshold = best; return rc; }
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && rc == GF2E_OK; ++r) rc = gf2e_mul_batched(handle, count, A, B, C, e, f, stream);
+        (void)hipEventRecord(e1, s);
+        if (rc || hipEventSynchronize(e1) != hipSuccess) { c->batch_threshold = best; return rc ? rc : GF2E_EDEVICE; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = th; }
+        c->release_batches();  // each candidate holds its own plane arena
+    }
+    c->event_pool.push_back(e0);
+    c->event_pool.push_back(e1);
+    c->batch_threshold = best;
+    return GF2E_OK;
+}
+
+}  // extern "C"

@@ -61,7 +61,11 @@ struct Ctx {
 
     std::map<uint64_t, int> tune;  // size bucket -> product kernel
 
-    std::vector<BatchGraph*> batches;  // cached batched graphs (owned)
+    std::vector<BatchGraph*> batches;  // cached batched graphs (owned), least recent first
+    int64_t batch_threshold = 384;     // min(m, n) at which a product takes 256x256 tiles
+    int64_t batch_builds = 0;
+    int64_t last_batch_items[2] = {0, 0};
+    int64_t last_batch_arena = 0;
 
     hipEvent_t get_event();
     void order_stream(hipStream_t s);

@@ -48,20 +48,16 @@ struct MfmaTile {
     static_assert(WM % 16 == 0 && BM % WM == 0 && BN % WN == 0, "tile shape");
 };
 
+// One BM x BN tile of P = Ahat * Bhat^T (planes already offset to product s).
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfma_kernel(
-    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
-    int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
+__device__ inline void mfma_tile(uint4 (&lds)[2][8][BM + BN], const uint64_t* __restrict__ Apl,
+                                 const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
+                                 int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
 {
     using TL = MfmaTile<BM, BN, WM, WN>;
     constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
-    // Two stages of 8 chunk-major arrays: lds[stage][chunk][row], 16 B each.
-    __shared__ uint4 lds[2][8][TL::kRows];
-
-    const int s = blockIdx.z;
-    const int tile_m = blockIdx.y, tile_n = blockIdx.x;
-    const uint64_t* Ap = Apl + int64_t(s) * K64p * Mp + int64_t(tile_m) * BM;
-    const uint64_t* Bp = Bpl + int64_t(s) * K64p * Np + int64_t(tile_n) * BN;
+    const uint64_t* Ap = Apl + int64_t(tile_m) * BM;
+    const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
     const int K128 = int(K64p / 2);
@@ -133,7 +129,6 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
     // The parity ballots of register r give 16 bits of each of 4 rows; lane L
     // (< 16 * WN/64) assembles row 4*(L&3) + ((L>>2)&3), word L>>4.
     const int64_t ldp = Np / 64;
-    uint64_t* Ps = P + int64_t(s) * Mp * ldp;
     const int rg = lane & 3, rr = (lane >> 2) & 3, wsel = lane >> 4;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
@@ -151,6 +146,47 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
             Ps[row * ldp + colw] = word;
         }
     }
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfma_kernel(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
+    int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
+{
+    // Two stages of 8 chunk-major arrays: lds[stage][chunk][row], 16 B each.
+    __shared__ uint4 lds[2][8][BM + BN];
+    const int64_t s = blockIdx.z;
+    mfma_tile<BM, BN, WM, WN>(lds, Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64),
+                              Mp, Np, K64p, blockIdx.y, blockIdx.x);
+}
+
+// Persistent grouped form: every workgroup takes work items (product, plane,
+// tile) in list order from a global counter until the list is exhausted.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfma_persistent(
+    const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
+    int* __restrict__ counter)
+{
+    __shared__ uint4 lds[2][8][BM + BN];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const BatchProduct& P = prods[w.prod];
+        const int64_t s = w.plane;
+        mfma_tile<BM, BN, WM, WN>(lds, P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
+                                  P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
+                                  w.tile_n);
+    }
+}
+
+__global__ void reset_counters_kernel(int* counters, int n)
+{
+    if (int(threadIdx.x) < n) counters[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -259,7 +295,56 @@ hipError_t launch_mfma(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t
     return hipGetLastError();
 }
 
+template <int BM, int BN, int WM, int WN>
+int persistent_blocks()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_mfma_persistent<BM, BN, WM, WN>,
+                                                     MfmaTile<BM, BN, WM, WN>::kThreads, 0) != hipSuccess)
+        return 0;
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
 }  // namespace
+
+int persistent_grid(int kind)
+{
+    switch (kind) {
+        case GEMM_MFMA_256x256_W8: return persistent_blocks<256, 256, 128, 64>();
+        case GEMM_MFMA_128x128: return persistent_blocks<128, 128, 64, 64>();
+        default: return 0;
+    }
+}
+
+hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const WorkItem* items,
+                                  int nitems, int* counter, int grid, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (grid <= 0) return hipErrorInvalidValue;
+    switch (kind) {
+        case GEMM_MFMA_256x256_W8:
+            hipLaunchKernelGGL((gemm_mfma_persistent<256, 256, 128, 64>), dim3(grid),
+                               dim3(MfmaTile<256, 256, 128, 64>::kThreads), 0, s, prods, items, nitems,
+                               counter);
+            break;
+        case GEMM_MFMA_128x128:
+            hipLaunchKernelGGL((gemm_mfma_persistent<128, 128, 64, 64>), dim3(grid),
+                               dim3(MfmaTile<128, 128, 64, 64>::kThreads), 0, s, prods, items, nitems,
+                               counter);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(int* counters, int n, hipStream_t s)
+{
+    if (n <= 0 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, counters, n);
+    return hipGetLastError();
+}
 
 GemmShape gemm_shape(int kind)
 {
@@ -269,6 +354,7 @@ GemmShape gemm_shape(int kind)
         case GEMM_MFMA_256x128: return {256, 128};
         case GEMM_MFMA_64x64: return {64, 64};
         case GEMM_VALU_128x128: return {kValuTile, kValuTile};
+        case GEMM_MFMA_256x256_W8: return {256, 256};
         default: return {0, 0};
     }
 }
@@ -281,6 +367,7 @@ const char* gemm_name(int kind)
         case GEMM_MFMA_256x128: return "mfma_i8_256x128";
         case GEMM_MFMA_64x64: return "mfma_i8_64x64";
         case GEMM_VALU_128x128: return "valu_xor_128x128";
+        case GEMM_MFMA_256x256_W8: return "mfma_i8_256x256_w8";
         default: return "unknown";
     }
 }
@@ -299,6 +386,8 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
             return launch_mfma<256, 128, 128, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_MFMA_64x64:
             return launch_mfma<64, 64, 64, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_MFMA_256x256_W8:
+            return launch_mfma<256, 256, 128, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_VALU_128x128: {
             const int tm = int(ceil_div(m, kValuTile)), tn = int(ceil_div(n, kValuTile));
             if (tm * int64_t(kValuTile) > Mp || tn * int64_t(kValuTile) > Np) return hipErrorInvalidValue;

@@ -32,7 +32,8 @@ enum GemmKind : int {
     GEMM_MFMA_256x128 = 2,  // int8 MFMA, 4 waves of 128x64
     GEMM_MFMA_64x64 = 3,    // int8 MFMA, 1 wave of 64x64
     GEMM_VALU_128x128 = 4,  // AND/XOR on packed words, 4 waves of 64x64
-    GEMM_NUM_KINDS = 5
+    GEMM_MFMA_256x256_W8 = 5,  // int8 MFMA, 8 waves of 128x64
+    GEMM_NUM_KINDS = 6
 };
 
 struct GemmShape {
@@ -57,6 +58,41 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
 // write C (m x n elements).
 hipError_t launch_combine(int e, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
                           int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s);
+// One product of a batch, as the batched kernels read it from device memory.
+struct BatchProduct {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    int64_t m, k, n;
+    int64_t Mp, Np, K64p;
+    uint64_t* Apl;  // operand and product planes of this product (batch arena)
+    uint64_t* Bpl;
+    uint64_t* P;
+    int32_t e, T;
+    uint32_t f;
+    int32_t slice_a_blocks;  // 256-thread jobs of A-side slicing (0 when k = 0)
+    int32_t slice_b_blocks;
+    int32_t combine_blocks;
+};
+
+// One tile of one plane product in a persistent launch.
+struct WorkItem {
+    int32_t prod, plane, tile_m, tile_n;
+};
+
+hipError_t launch_batched_slice(const BatchProduct* prods, int count, int max_blocks, int* err,
+                                hipStream_t s);
+hipError_t launch_batched_combine(const BatchProduct* prods, int count, int max_blocks,
+                                  hipStream_t s);
+int batch_threads_per_block();
+// Persistent grouped products: workgroups take items in order from *counter
+// until it passes nitems.  kind: GEMM_MFMA_256x256_W8 or GEMM_MFMA_128x128.
+hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const WorkItem* items,
+                                  int nitems, int* counter, int grid, hipStream_t s);
+int persistent_grid(int kind);  // workgroups that fill the device once
+hipError_t launch_reset_counters(int* counters, int n, hipStream_t s);
+
 // C = 0 (the k = 0 product).
 hipError_t launch_zero(void* C, int64_t rows, int64_t cols, int64_t ld, int elem_bytes,
                        hipStream_t s);

@@ -60,16 +60,13 @@ __device__ inline void store_operands(const uint64_t (&planes)[E], uint64_t* dst
     }
 }
 
-// Row slicing: thread (r, kw) reads A[r][64kw .. 64kw+63].
+// Row slicing of one plane word: row r of A, k-bits [64kw, 64kw+64).
 template <int E>
-__global__ __launch_bounds__(kThreads) void slice_rows_kernel(
-    const void* __restrict__ A, int64_t lda, int64_t m, int64_t k, uint64_t* __restrict__ planes,
-    int64_t Mp, int64_t K64p, int* __restrict__ err)
+__device__ inline void slice_row_word(const void* __restrict__ A, int64_t lda, int64_t m, int64_t k,
+                                      uint64_t* __restrict__ planes, int64_t Mp, int64_t K64p,
+                                      int* __restrict__ err, int64_t r, int64_t kw)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
-    const int64_t r = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    const int64_t kw = blockIdx.y;
-    if (r >= Mp) return;
     uint64_t lo[8] = {}, hi[8] = {};
     bool bad = false;
     const int64_t c0 = kw * 64;
@@ -106,17 +103,14 @@ __global__ __launch_bounds__(kThreads) void slice_rows_kernel(
     store_operands<E>(pl, planes + kw * Mp + r, K64p * Mp);
 }
 
-// Column slicing: thread (j, kw) reads B[64kw .. 64kw+63][j]; consecutive
-// threads take consecutive columns, so every load instruction is coalesced.
+// Column slicing of one plane word: column j of B, k-bits [64kw, 64kw+64).
+// Consecutive threads take consecutive columns, so every load is coalesced.
 template <int E>
-__global__ __launch_bounds__(kThreads) void slice_cols_kernel(
-    const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint64_t* __restrict__ planes,
-    int64_t Np, int64_t K64p, int* __restrict__ err)
+__device__ inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
+                                      uint64_t* __restrict__ planes, int64_t Np, int64_t K64p,
+                                      int* __restrict__ err, int64_t j, int64_t kw)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
-    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    const int64_t kw = blockIdx.y;
-    if (j >= Np) return;
     uint64_t lo[8] = {}, hi[8] = {};
     bool bad = false;
     const int64_t r0 = kw * 64;
@@ -146,23 +140,19 @@ __global__ __launch_bounds__(kThreads) void slice_cols_kernel(
     store_operands<E>(pl, planes + kw * Np + j, K64p * Np);
 }
 
-// Combine: thread (i, w) turns word w of row i of every product plane into
-// 64 elements of C.
+// Combine of one word: word w of row i of every product plane becomes 64
+// elements of C.  k0 set: the product has an empty inner dimension, C = 0.
 template <int E>
-__global__ __launch_bounds__(kThreads) void combine_kernel(
-    const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp, int64_t m, int64_t n, uint32_t f,
-    void* __restrict__ C, int64_t ldc)
+__device__ inline void combine_word(const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp,
+                                    int64_t n, uint32_t f, void* __restrict__ C, int64_t ldc,
+                                    int64_t i, int64_t w, bool k0)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     constexpr Schedule S = build_schedule(E);
     constexpr int D = 2 * E - 1;
-    const int64_t nw = (n + 63) / 64;
-    const int64_t w = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (w >= nw) return;
-    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
     uint64_t p[S.t];
 #pragma unroll
-    for (int s = 0; s < S.t; ++s) p[s] = P[s * Mp * ldp + i * ldp + w];
+    for (int s = 0; s < S.t; ++s) p[s] = k0 ? 0ull : P[s * Mp * ldp + i * ldp + w];
 
     // Coefficient planes of the polynomial product: C~_d = XOR_{s in w[d]} P_s.
     uint64_t c[D];
@@ -217,11 +207,96 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(
                             (uint32_t(out[16 * q + 4 * h + 3]) << 24);
                 v[q] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
             }
-            continue;
+            return;
         }
     }
     for (int b = 0; b < valid; ++b) dst[b] = out[b];
+}
+
+template <int E>
+__global__ __launch_bounds__(kThreads) void slice_rows_kernel(
+    const void* __restrict__ A, int64_t lda, int64_t m, int64_t k, uint64_t* __restrict__ planes,
+    int64_t Mp, int64_t K64p, int* __restrict__ err)
+{
+    const int64_t r = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (r >= Mp) return;
+    slice_row_word<E>(A, lda, m, k, planes, Mp, K64p, err, r, blockIdx.y);
+}
+
+template <int E>
+__global__ __launch_bounds__(kThreads) void slice_cols_kernel(
+    const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint64_t* __restrict__ planes,
+    int64_t Np, int64_t K64p, int* __restrict__ err)
+{
+    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (j >= Np) return;
+    slice_col_word<E>(B, ldb, k, n, planes, Np, K64p, err, j, blockIdx.y);
+}
+
+template <int E>
+__global__ __launch_bounds__(kThreads) void combine_kernel(
+    const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp, int64_t m, int64_t n, uint32_t f,
+    void* __restrict__ C, int64_t ldc)
+{
+    const int64_t nw = (n + 63) / 64;
+    const int64_t w = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (w >= nw) return;
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y)
+        combine_word<E>(P, Mp, ldp, n, f, C, ldc, i, w, false);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: blockIdx.y selects the product, blockIdx.x a 256-thread job
+// of that product (blocks past the product's job count return at once).
+// ---------------------------------------------------------------------------
+#define GF2E_SWITCH_E(e, CALL) \
+    switch (e) {               \
+        case 2: CALL(2); break;  \
+        case 3: CALL(3); break;  \
+        case 4: CALL(4); break;  \
+        case 5: CALL(5); break;  \
+        case 6: CALL(6); break;  \
+        case 7: CALL(7); break;  \
+        case 8: CALL(8); break;  \
+        case 9: CALL(9); break;  \
+        case 10: CALL(10); break; \
+        default: break;          \
     }
+
+__global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProduct* __restrict__ prods,
+                                                                 int* __restrict__ err)
+{
+    const BatchProduct& P = prods[blockIdx.y];
+    int64_t job = blockIdx.x;
+    if (job < P.slice_a_blocks) {
+        const int64_t rb_count = P.Mp / kThreads;
+        const int64_t r = (job % rb_count) * kThreads + threadIdx.x, kw = job / rb_count;
+#define S_(E) slice_row_word<E>(P.A, P.lda, P.m, P.k, P.Apl, P.Mp, P.K64p, err, r, kw)
+        GF2E_SWITCH_E(P.e, S_)
+#undef S_
+        return;
+    }
+    job -= P.slice_a_blocks;
+    if (job < P.slice_b_blocks) {
+        const int64_t cb_count = P.Np / kThreads;
+        const int64_t j = (job % cb_count) * kThreads + threadIdx.x, kw = job / cb_count;
+#define S_(E) slice_col_word<E>(P.B, P.ldb, P.k, P.n, P.Bpl, P.Np, P.K64p, err, j, kw)
+        GF2E_SWITCH_E(P.e, S_)
+#undef S_
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void batched_combine_kernel(const BatchProduct* __restrict__ prods)
+{
+    const BatchProduct& P = prods[blockIdx.y];
+    if (int64_t(blockIdx.x) >= P.combine_blocks) return;
+    const int64_t nw = (P.n + 63) / 64;
+    const int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (idx >= P.m * nw) return;
+    const int64_t i = idx / nw, w = idx % nw;
+#define C_(E) combine_word<E>(P.P, P.Mp, P.Np / 64, P.n, P.f, P.C, P.ldc, i, w, P.k == 0)
+    GF2E_SWITCH_E(P.e, C_)
+#undef C_
 }
 
 __global__ void zero_kernel(uint8_t* C, int64_t rows, int64_t row_bytes, int64_t ld_bytes)
@@ -295,5 +370,26 @@ hipError_t launch_zero(void* C, int64_t rows, int64_t cols, int64_t ld, int elem
                        row_bytes, ld * elem_bytes);
     return hipGetLastError();
 }
+
+}  // namespace gf2e
+
+namespace gf2e {
+
+hipError_t launch_batched_slice(const BatchProduct* prods, int count, int max_blocks, int* err,
+                                hipStream_t s)
+{
+    if (count <= 0 || max_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batched_slice_kernel, dim3(max_blocks, count), dim3(kThreads), 0, s, prods, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_combine(const BatchProduct* prods, int count, int max_blocks, hipStream_t s)
+{
+    if (count <= 0 || max_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batched_combine_kernel, dim3(max_blocks, count), dim3(kThreads), 0, s, prods);
+    return hipGetLastError();
+}
+
+int batch_threads_per_block() { return kThreads; }
 
 }  // namespace gf2e
