@@ -50,11 +50,13 @@ struct MfmaTile {
 
 // One BM x BN tile of P = Ahat * Bhat^T (planes already offset to product s).
 template <int BM, int BN, int WM, int WN>
-__device__ inline void mfma_tile(uint4 (&lds)[2][8][BM + BN], const uint64_t* __restrict__ Apl,
-                                 const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
-                                 int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
+__device__ __attribute__((always_inline)) inline void mfma_tile(const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl,
+                                 uint64_t* __restrict__ Ps, int64_t Mp, int64_t Np, int64_t K64p,
+                                 int tile_m, int tile_n)
 {
     using TL = MfmaTile<BM, BN, WM, WN>;
+    // Two stages of 8 chunk-major arrays: lds[stage][chunk][row], 16 B each.
+    __shared__ uint4 lds[2][8][BM + BN];
     constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
     const uint64_t* Ap = Apl + int64_t(tile_m) * BM;
     const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
@@ -153,10 +155,8 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
     int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
 {
-    // Two stages of 8 chunk-major arrays: lds[stage][chunk][row], 16 B each.
-    __shared__ uint4 lds[2][8][BM + BN];
     const int64_t s = blockIdx.z;
-    mfma_tile<BM, BN, WM, WN>(lds, Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64),
+    mfma_tile<BM, BN, WM, WN>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64),
                               Mp, Np, K64p, blockIdx.y, blockIdx.x);
 }
 
@@ -167,7 +167,6 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
     const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
     int* __restrict__ counter)
 {
-    __shared__ uint4 lds[2][8][BM + BN];
     __shared__ int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -178,7 +177,7 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
         const WorkItem w = items[it];
         const BatchProduct& P = prods[w.prod];
         const int64_t s = w.plane;
-        mfma_tile<BM, BN, WM, WN>(lds, P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
+        mfma_tile<BM, BN, WM, WN>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
                                   P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
                                   w.tile_n);
     }
