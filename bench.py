@@ -20,8 +20,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_INT8_TOPS = 5000.0   # MI355X dense int8 MFMA, 5.0 POP/s
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, 8 TB/s
+
+# Roofline of each product kernel: (bound, peak, unit, ops counted per GF(2)
+# multiply-add).  MFMA peaks are MI355X's published dense figures for the
+# kernel's operand type; the VALU kernel's peak is derived from the unit
+# counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 3-input bitwise op
+# (acc ^= a & b) per 32 bit-products -> 1258.3 T bit-products/s.
+KERNEL_ROOFLINE = {
+    "mfma_i8": ("mfma", 5000.0, "TOP/s", 2.0),       # int8 dense, 5.0 POP/s
+    "mfma_fp4": ("mfma", 10100.0, "TFLOP/s", 2.0),   # fp4 dense, 10.1 PFLOP/s
+    "valu_xor": ("alu", 1258.3, "Tbit-MAC/s", 1.0),
+}
+
+
+def kernel_roofline(name):
+    for prefix, spec in KERNEL_ROOFLINE.items():
+        if name.startswith(prefix):
+            return spec
+    raise KeyError(name)
+
+
+def measured_traffic(workload_name, kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None if there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        entry = json.load(open(path))[workload_name][kernel_name]
+        src = open(os.path.join(ROOT, entry["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != entry["source_sha256"]:
+        return None
+    return entry["traffic_bytes"]
 
 
 def parse_args():
@@ -187,7 +219,7 @@ def main():
     args = parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not "
-                                   "supported (products shard by output rows, see DESIGN.md)",
+                                   "supported by this benchmark",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
@@ -242,12 +274,16 @@ def main():
 
     T = g.num_products(e)
     prod_ms = stages["products"]
-    ops = 2.0 * T * m * n * k  # int8 MFMA ops: one 0/1 multiply-add = 2 ops
+    kname = g.kernel_names()[kind]
+    bound, peak, unit, ops_per_mac = kernel_roofline(kname)
+    ops = ops_per_mac * T * m * n * k  # algorithmic: t(e) GF(2) products of m x k x n
     achieved = ops / (prod_ms / 1e3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_INT8_TOPS,
-                "unit": "TOP/s", "frac": round(achieved / PEAK_INT8_TOPS, 4), "traffic": None,
-                "kernel": g.kernel_names()[kind], "avg_launch_ms": round(prod_ms, 4),
-                "algorithmic_ops_per_launch": ops}
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(args.workload, kname),
+                "kernel": kname, "avg_launch_ms": round(prod_ms, 4),
+                "algorithmic_ops_per_launch": ops,
+                "algorithmic_bytes_per_launch": 8 * T * ((-(-k // 64)) * (m + n) + m * (-(-n // 64)))}
     # HBM-bound stages: algorithmic bytes (elements in/out + planes written/read).
     esz = 1 if e <= 8 else 2
     kw = 2 * -(-k // 128)

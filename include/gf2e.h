@@ -73,7 +73,9 @@ enum {
     GF2E_KERNEL_MFMA_256x128 = 2, /* int8 MFMA, 256x128 tiles */
     GF2E_KERNEL_MFMA_64 = 3,      /* int8 MFMA, 64x64 tiles */
     GF2E_KERNEL_VALU_128 = 4,     /* AND/XOR on packed words, 128x128 tiles */
-    GF2E_KERNEL_MFMA_256_W8 = 5   /* int8 MFMA, 256x256 tiles, 8 waves of 128x64 */
+    GF2E_KERNEL_MFMA_256_W8 = 5,  /* int8 MFMA, 256x256 tiles, 8 waves of 128x64 */
+    GF2E_KERNEL_FP4_256_W8 = 6,   /* fp4 MFMA (0/1 nibbles, exact count in f32), 256x256, k < 2^24 */
+    GF2E_KERNEL_FP4_128 = 7       /* fp4 MFMA, 128x128 tiles, k < 2^24 */
 };
 
 typedef struct {

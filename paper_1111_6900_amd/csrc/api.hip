@@ -177,6 +177,12 @@ int default_kind(int T, int64_t m, int64_t n)
     return GEMM_MFMA_64x64;
 }
 
+bool kind_supports(int kind, const Plan& p)
+{
+    const bool fp4 = kind == GEMM_FP4_256x256_W8 || kind == GEMM_FP4_128x128;
+    return !fp4 || p.K64p * 64 <= (int64_t(1) << 24);
+}
+
 int Ctx::choose_kind(const Plan& p)
 {
     if (forced_kind >= 0) return forced_kind;
@@ -268,7 +274,8 @@ int Ctx::run_plan(const Plan& p, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat*
     if (cfg.autotune && forced_kind < 0 && !tune.count(bucket_key(p.T, p.m, p.k, p.n))) {
         if ((rc = tune_now(p, s))) return rc;
     }
-    const int kind = choose_kind(p);
+    int kind = choose_kind(p);
+    if (!kind_supports(kind, p)) kind = GEMM_MFMA_256x256_W8;  // f32 counts would not be exact
     uint64_t* Apl = static_cast<uint64_t*>(ws);
     uint64_t* Bpl = Apl + p.a_bytes / 8;
     uint64_t* P = Bpl + p.b_bytes / 8;

@@ -21,6 +21,13 @@
 
 namespace gf2e {
 
+namespace {
+// Tile classes: {large, small} x {fp4 (k < 2^24), int8}.
+constexpr int kNumClasses = 4;
+constexpr int kClassKinds[kNumClasses] = {GEMM_FP4_256x256_W8, GEMM_FP4_128x128, GEMM_MFMA_256x256_W8,
+                                          GEMM_MFMA_128x128};
+}  // namespace
+
 struct BatchGraph {
     std::vector<uint8_t> key;
     int count = 0;
@@ -29,8 +36,8 @@ struct BatchGraph {
     BatchProduct* d_prods = nullptr;
     WorkItem* d_items = nullptr;
     int* d_counters = nullptr;
-    int n_items[2] = {0, 0};
-    int grid[2] = {0, 0};
+    int n_items[kNumClasses] = {};
+    int grid[kNumClasses] = {};
     int max_slice_blocks = 0, max_combine_blocks = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -51,7 +58,6 @@ struct BatchGraph {
 namespace {
 
 constexpr int kMaxCachedBatches = 8;
-constexpr int kClassKinds[2] = {GEMM_MFMA_256x256_W8, GEMM_MFMA_128x128};
 
 template <class T>
 void put(std::vector<uint8_t>& key, const T& v)
@@ -119,11 +125,12 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
     }
 
     // Work lists: size class by the smaller output dimension.
-    std::vector<WorkItem> items[2];
+    std::vector<WorkItem> items[kNumClasses];
     for (size_t i = 0; i < prods.size(); ++i) {
         const BatchProduct& d = prods[i];
         if (d.k == 0) continue;
-        const int cls = std::min(d.m, d.n) >= c->batch_threshold ? 0 : 1;
+        const int cls = (std::min(d.m, d.n) >= c->batch_threshold ? 0 : 1) +
+                        (d.K64p * 64 <= (int64_t(1) << 24) ? 0 : 2);
         const GemmShape sh = gemm_shape(kClassKinds[cls]);
         const int tm = int(ceil_div(d.m, sh.bm)), tn = int(ceil_div(d.n, sh.bn));
         for (int s = 0; s < d.T; ++s)
@@ -131,7 +138,7 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
                 for (int b = 0; b < tn; ++b) items[cls].push_back({int32_t(i), s, a, b});
     }
     const char* shuffle = std::getenv("GF2E_BATCH_SHUFFLE");
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < kNumClasses; ++cls) {
         auto& v = items[cls];
         if (shuffle && *shuffle) {
             std::mt19937_64 rng(std::strtoull(shuffle, nullptr, 10));
@@ -147,32 +154,36 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
     }
 
     // Device copies of the descriptors and work lists.
-    const size_t nall = items[0].size() + items[1].size();
+    size_t nall = 0, item_off[kNumClasses] = {};
+    for (int cls = 0; cls < kNumClasses; ++cls) {
+        item_off[cls] = nall;
+        nall += items[cls].size();
+    }
     if (hipMalloc(&bg->d_prods, sizeof(BatchProduct) * std::max<size_t>(prods.size(), 1)) != hipSuccess ||
         hipMalloc(&bg->d_items, sizeof(WorkItem) * std::max<size_t>(nall, 1)) != hipSuccess ||
-        hipMalloc(&bg->d_counters, 2 * sizeof(int)) != hipSuccess) {
+        hipMalloc(&bg->d_counters, kNumClasses * sizeof(int)) != hipSuccess) {
         (void)hipGetLastError();
         return GF2E_ENOMEM;
     }
-    if ((!prods.empty() && hipMemcpy(bg->d_prods, prods.data(), sizeof(BatchProduct) * prods.size(),
-                                     hipMemcpyHostToDevice) != hipSuccess) ||
-        (!items[0].empty() && hipMemcpy(bg->d_items, items[0].data(), sizeof(WorkItem) * items[0].size(),
-                                        hipMemcpyHostToDevice) != hipSuccess) ||
-        (!items[1].empty() && hipMemcpy(bg->d_items + items[0].size(), items[1].data(),
-                                        sizeof(WorkItem) * items[1].size(), hipMemcpyHostToDevice) != hipSuccess))
+    if (!prods.empty() && hipMemcpy(bg->d_prods, prods.data(), sizeof(BatchProduct) * prods.size(),
+                                    hipMemcpyHostToDevice) != hipSuccess)
         return GF2E_EDEVICE;
+    for (int cls = 0; cls < kNumClasses; ++cls)
+        if (!items[cls].empty() &&
+            hipMemcpy(bg->d_items + item_off[cls], items[cls].data(), sizeof(WorkItem) * items[cls].size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return GF2E_EDEVICE;
 
     // Capture: reset counters, grouped slicing, the persistent products of
     // each size class, grouped combining.
     if (hipStreamCreateWithFlags(&bg->cap, hipStreamNonBlocking) != hipSuccess) return GF2E_EDEVICE;
     if (hipStreamBeginCapture(bg->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return GF2E_EDEVICE;
-    hipError_t err = launch_reset_counters(bg->d_counters, 2, bg->cap);
+    hipError_t err = launch_reset_counters(bg->d_counters, kNumClasses, bg->cap);
     if (err == hipSuccess)
         err = launch_batched_slice(bg->d_prods, bg->count, bg->max_slice_blocks, c->d_err, bg->cap);
-    for (int cls = 0; cls < 2 && err == hipSuccess; ++cls)
-        err = launch_persistent_gemm(kClassKinds[cls], bg->d_prods,
-                                     bg->d_items + (cls ? items[0].size() : 0), bg->n_items[cls],
-                                     bg->d_counters + cls, bg->grid[cls], bg->cap);
+    for (int cls = 0; cls < kNumClasses && err == hipSuccess; ++cls)
+        err = launch_persistent_gemm(kClassKinds[cls], bg->d_prods, bg->d_items + item_off[cls],
+                                     bg->n_items[cls], bg->d_counters + cls, bg->grid[cls], bg->cap);
     if (err == hipSuccess)
         err = launch_batched_combine(bg->d_prods, bg->count, bg->max_combine_blocks, bg->cap);
     hipGraph_t graph = nullptr;
@@ -255,8 +266,8 @@ int gf2e_mul_batched(gf2e_ctx* handle, int count, const gf2e_mat* A, const gf2e_
         err = hipGraphLaunch(bg->exec, s);
     }
     c->mark_used(s);
-    c->last_batch_items[0] = bg->n_items[0];
-    c->last_batch_items[1] = bg->n_items[1];
+    c->last_batch_items[0] = bg->n_items[0] + bg->n_items[2];
+    c->last_batch_items[1] = bg->n_items[1] + bg->n_items[3];
     c->last_batch_arena = bg->arena_bytes;
     return err == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
 }

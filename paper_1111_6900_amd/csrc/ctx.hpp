@@ -38,6 +38,7 @@ bool overlaps(const gf2e_mat* X, const gf2e_mat* Y, int esz);
 int validate_mul(const gf2e_mat* A, const gf2e_mat* B, const gf2e_mat* C, int e, uint32_t f);
 Plan make_plan(int e, int64_t m, int64_t k, int64_t n);
 int default_kind(int T, int64_t m, int64_t n);
+bool kind_supports(int kind, const Plan& p);
 
 struct BatchGraph;  // defined in batch.hip
 

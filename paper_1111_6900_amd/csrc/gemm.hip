@@ -189,6 +189,162 @@ __global__ void reset_counters_kernel(int* counters, int n)
 }
 
 // ---------------------------------------------------------------------------
+// FP4 MFMA path (v_mfma_scale_f32_16x16x128_f8f6f4, both operands e2m1): every
+// bit becomes a nibble that is 0 or 1.0 (0b0010), scales are 2^0, so each
+// f32 accumulator holds the exact count of common ones (exact below 2^24;
+// launches with more k are refused).  The low bit of that count is the GF(2)
+// product, as in the int8 path, at twice its MFMA rate and half its staging
+// bytes.  A stage holds KB consecutive 128-bit k-blocks; block b of a row is
+// stored as 4 chunks of 32 nibbles, chunk c from 32-bit word c of the block.
+// ---------------------------------------------------------------------------
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int64_t kFp4MaxK = int64_t(1) << 24;
+
+// Chunk of 32-bit word h: nibble j of dword q is 1.0 iff bit 4j+q of h is set.
+__device__ inline uint4 expand_fp4(uint32_t h)
+{
+    const uint32_t M = 0x22222222u;
+    return make_uint4((h << 1) & M, h & M, (h >> 1) & M, (h >> 2) & M);
+}
+
+template <int BM, int BN, int WM, int WN, int KB>
+__device__ __attribute__((always_inline)) inline void fp4_tile(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
+    int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
+    constexpr int CH = 4 * KB;  // chunks per row per stage
+    __shared__ uint4 lds[2][CH][BM + BN];
+    const uint64_t* Ap = Apl + int64_t(tile_m) * BM;
+    const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
+    const int nstages = int((K64p + 2 * KB - 1) / (2 * KB));
+
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    uint64_t stg[RPT][2 * KB];
+    auto gload = [&](int st) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < TL::kRows) {
+                const bool isA = r < BM;
+                const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
+                const int64_t ld = isA ? Mp : Np;
+#pragma unroll
+                for (int w = 0; w < 2 * KB; ++w) {
+                    const int64_t kw = int64_t(st) * 2 * KB + w;
+                    stg[q][w] = kw < K64p ? src[kw * ld] : 0ull;
+                }
+            }
+        }
+    };
+    auto expand_store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < TL::kRows) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c)
+                    lds[buf][c][r] = expand_fp4(uint32_t(stg[q][c >> 1] >> (32 * (c & 1))));
+            }
+        }
+    };
+
+    gload(0);
+    expand_store(0);
+    __syncthreads();
+    const int g = lane >> 4, l16 = lane & 15;
+    for (int st = 0; st < nstages; ++st) {
+        const int buf = st & 1;
+        const bool more = st + 1 < nstages;
+        if (more) gload(st + 1);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const int c = 4 * kb + g;
+            v8i a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const uint4 x = lds[buf][c][wr * WM + 16 * i + l16];
+                a[i] = v8i{int(x.x), int(x.y), int(x.z), int(x.w), 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const uint4 x = lds[buf][c][BM + wc * WN + 16 * j + l16];
+                b[j] = v8i{int(x.x), int(x.y), int(x.z), int(x.w), 0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4,
+                                                                                0, 127, 0, 127);
+        }
+        if (more) expand_store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Same output layout and packing as the int8 tile.
+    const int64_t ldp = Np / 64;
+    const int rg = lane & 3, rr = (lane >> 2) & 3, wsel = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64((int(acc[i][j][r]) & 1) != 0);
+                if (rr == r && wsel == (j >> 2)) word |= ((bal >> (16 * rg)) & 0xFFFFull) << (16 * (j & 3));
+            }
+        if (lane < 16 * (WN / 64)) {
+            const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + 4 * rg + rr;
+            const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + wsel;
+            Ps[row * ldp + colw] = word;
+        }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int KB>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_fp4_kernel(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
+    int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
+{
+    const int64_t s = blockIdx.z;
+    fp4_tile<BM, BN, WM, WN, KB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
+                                 Np, K64p, blockIdx.y, blockIdx.x);
+}
+
+template <int BM, int BN, int WM, int WN, int KB>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_fp4_persistent(
+    const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
+    int* __restrict__ counter)
+{
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const BatchProduct& P = prods[w.prod];
+        const int64_t s = w.plane;
+        fp4_tile<BM, BN, WM, WN, KB>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
+                                     P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
+                                     w.tile_n);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // VALU path: WG tile 128x128, 4 waves of 64x64, thread (ty, tx) of its wave
 // owns rows 8*ty + r and columns tx + 8*c (r, c < 8), so that one ballot per
 // (r, c) yields whole bytes of output words.
@@ -294,6 +450,29 @@ hipError_t launch_mfma(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t
     return hipGetLastError();
 }
 
+template <int BM, int BN, int WM, int WN, int KB>
+hipError_t launch_fp4(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P, int64_t m,
+                      int64_t n, int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    const int tm = int(ceil_div(m, BM)), tn = int(ceil_div(n, BN));
+    if (tm * int64_t(BM) > Mp || tn * int64_t(BN) > Np || K64p * 64 > kFp4MaxK) return hipErrorInvalidValue;
+    dim3 grid(tn, tm, T);
+    hipLaunchKernelGGL((gemm_fp4_kernel<BM, BN, WM, WN, KB>), grid, dim3(TL::kThreads), 0, st, Apl, Bpl,
+                       P, Mp, Np, K64p, tm, tn);
+    return hipGetLastError();
+}
+
+template <class Kern>
+int blocks_filling_device(Kern kernel, int threads)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) return 0;
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
 template <int BM, int BN, int WM, int WN>
 int persistent_blocks()
 {
@@ -313,6 +492,12 @@ int persistent_grid(int kind)
     switch (kind) {
         case GEMM_MFMA_256x256_W8: return persistent_blocks<256, 256, 128, 64>();
         case GEMM_MFMA_128x128: return persistent_blocks<128, 128, 64, 64>();
+        case GEMM_FP4_256x256_W8:
+            return blocks_filling_device(gemm_fp4_persistent<256, 256, 128, 64, 2>,
+                                         MfmaTile<256, 256, 128, 64>::kThreads);
+        case GEMM_FP4_128x128:
+            return blocks_filling_device(gemm_fp4_persistent<128, 128, 64, 64, 2>,
+                                         MfmaTile<128, 128, 64, 64>::kThreads);
         default: return 0;
     }
 }
@@ -330,6 +515,16 @@ hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const Wor
             break;
         case GEMM_MFMA_128x128:
             hipLaunchKernelGGL((gemm_mfma_persistent<128, 128, 64, 64>), dim3(grid),
+                               dim3(MfmaTile<128, 128, 64, 64>::kThreads), 0, s, prods, items, nitems,
+                               counter);
+            break;
+        case GEMM_FP4_256x256_W8:
+            hipLaunchKernelGGL((gemm_fp4_persistent<256, 256, 128, 64, 2>), dim3(grid),
+                               dim3(MfmaTile<256, 256, 128, 64>::kThreads), 0, s, prods, items, nitems,
+                               counter);
+            break;
+        case GEMM_FP4_128x128:
+            hipLaunchKernelGGL((gemm_fp4_persistent<128, 128, 64, 64, 2>), dim3(grid),
                                dim3(MfmaTile<128, 128, 64, 64>::kThreads), 0, s, prods, items, nitems,
                                counter);
             break;
@@ -354,6 +549,8 @@ GemmShape gemm_shape(int kind)
         case GEMM_MFMA_64x64: return {64, 64};
         case GEMM_VALU_128x128: return {kValuTile, kValuTile};
         case GEMM_MFMA_256x256_W8: return {256, 256};
+        case GEMM_FP4_256x256_W8: return {256, 256};
+        case GEMM_FP4_128x128: return {128, 128};
         default: return {0, 0};
     }
 }
@@ -367,6 +564,8 @@ const char* gemm_name(int kind)
         case GEMM_MFMA_64x64: return "mfma_i8_64x64";
         case GEMM_VALU_128x128: return "valu_xor_128x128";
         case GEMM_MFMA_256x256_W8: return "mfma_i8_256x256_w8";
+        case GEMM_FP4_256x256_W8: return "mfma_fp4_256x256_w8";
+        case GEMM_FP4_128x128: return "mfma_fp4_128x128";
         default: return "unknown";
     }
 }
@@ -387,6 +586,10 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
             return launch_mfma<64, 64, 64, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_MFMA_256x256_W8:
             return launch_mfma<256, 256, 128, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_FP4_256x256_W8:
+            return launch_fp4<256, 256, 128, 64, 2>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+        case GEMM_FP4_128x128:
+            return launch_fp4<128, 128, 64, 64, 2>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_VALU_128x128: {
             const int tm = int(ceil_div(m, kValuTile)), tn = int(ceil_div(n, kValuTile));
             if (tm * int64_t(kValuTile) > Mp || tn * int64_t(kValuTile) > Np) return hipErrorInvalidValue;

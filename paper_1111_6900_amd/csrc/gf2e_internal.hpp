@@ -33,7 +33,9 @@ enum GemmKind : int {
     GEMM_MFMA_64x64 = 3,    // int8 MFMA, 1 wave of 64x64
     GEMM_VALU_128x128 = 4,  // AND/XOR on packed words, 4 waves of 64x64
     GEMM_MFMA_256x256_W8 = 5,  // int8 MFMA, 8 waves of 128x64
-    GEMM_NUM_KINDS = 6
+    GEMM_FP4_256x256_W8 = 6,   // fp4 MFMA, 8 waves of 128x64 (k < 2^24)
+    GEMM_FP4_128x128 = 7,      // fp4 MFMA, 4 waves of 64x64 (k < 2^24)
+    GEMM_NUM_KINDS = 8
 };
 
 struct GemmShape {

@@ -62,7 +62,7 @@ __device__ inline void store_operands(const uint64_t (&planes)[E], uint64_t* dst
 
 // Row slicing of one plane word: row r of A, k-bits [64kw, 64kw+64).
 template <int E>
-__device__ inline void slice_row_word(const void* __restrict__ A, int64_t lda, int64_t m, int64_t k,
+__device__ __attribute__((always_inline)) inline void slice_row_word(const void* __restrict__ A, int64_t lda, int64_t m, int64_t k,
                                       uint64_t* __restrict__ planes, int64_t Mp, int64_t K64p,
                                       int* __restrict__ err, int64_t r, int64_t kw)
 {
@@ -83,17 +83,21 @@ __device__ inline void slice_row_word(const void* __restrict__ A, int64_t lda, i
                     lo[2 * q + 1] = uint64_t(x.z) | (uint64_t(x.w) << 32);
                 }
             } else {
-                for (int64_t c = 0; c < valid; ++c)
-                    lo[c >> 3] |= uint64_t(row[c]) << (8 * (c & 7));
+#pragma unroll
+                for (int c = 0; c < 64; ++c)
+                    if (c < valid) lo[c >> 3] |= uint64_t(row[c]) << (8 * (c & 7));
             }
 #pragma unroll
             for (int g = 0; g < 8; ++g) bad |= bytes_out_of_field(lo[g], E);
         } else {
-            for (int64_t c = 0; c < valid; ++c) {
-                const uint32_t x = row[c];
-                bad |= (x >> E) != 0;
-                lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
-                hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));
+#pragma unroll
+            for (int c = 0; c < 64; ++c) {
+                if (c < valid) {
+                    const uint32_t x = row[c];
+                    bad |= (x >> E) != 0;
+                    lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
+                    hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));
+                }
             }
         }
     }
@@ -106,7 +110,7 @@ __device__ inline void slice_row_word(const void* __restrict__ A, int64_t lda, i
 // Column slicing of one plane word: column j of B, k-bits [64kw, 64kw+64).
 // Consecutive threads take consecutive columns, so every load is coalesced.
 template <int E>
-__device__ inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
+__device__ __attribute__((always_inline)) inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
                                       uint64_t* __restrict__ planes, int64_t Np, int64_t K64p,
                                       int* __restrict__ err, int64_t j, int64_t kw)
 {
@@ -117,16 +121,9 @@ __device__ inline void slice_col_word(const void* __restrict__ B, int64_t ldb, i
     if (j < n && r0 < k) {
         const elem_t* col = reinterpret_cast<const elem_t*>(B) + r0 * ldb + j;
         const int64_t valid = (k - r0) < 64 ? (k - r0) : 64;
-        if (valid == 64) {
 #pragma unroll
-            for (int c = 0; c < 64; ++c) {
-                const uint32_t x = col[c * ldb];
-                bad |= (x >> E) != 0;
-                lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
-                if constexpr (E > 8) hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));
-            }
-        } else {
-            for (int64_t c = 0; c < valid; ++c) {
+        for (int c = 0; c < 64; ++c) {
+            if (c < valid) {
                 const uint32_t x = col[c * ldb];
                 bad |= (x >> E) != 0;
                 lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
@@ -143,7 +140,7 @@ __device__ inline void slice_col_word(const void* __restrict__ B, int64_t ldb, i
 // Combine of one word: word w of row i of every product plane becomes 64
 // elements of C.  k0 set: the product has an empty inner dimension, C = 0.
 template <int E>
-__device__ inline void combine_word(const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp,
+__device__ __attribute__((always_inline)) inline void combine_word(const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp,
                                     int64_t n, uint32_t f, void* __restrict__ C, int64_t ldc,
                                     int64_t i, int64_t w, bool k0)
 {
@@ -210,7 +207,9 @@ __device__ inline void combine_word(const uint64_t* __restrict__ P, int64_t Mp, 
             return;
         }
     }
-    for (int b = 0; b < valid; ++b) dst[b] = out[b];
+#pragma unroll
+    for (int b = 0; b < 64; ++b)
+        if (b < valid) dst[b] = out[b];
 }
 
 template <int E>

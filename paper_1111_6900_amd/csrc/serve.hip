@@ -37,7 +37,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int kClassKinds[2] = {GEMM_MFMA_256x256_W8, GEMM_MFMA_128x128};
+// Tile classes: {large, small} x {fp4 (k < 2^24), int8}.
+constexpr int kNumClasses = 4;
+constexpr int kClassKinds[kNumClasses] = {GEMM_FP4_256x256_W8, GEMM_FP4_128x128, GEMM_MFMA_256x256_W8,
+                                          GEMM_MFMA_128x128};
 constexpr int kIterBuffers = 3;  // iterations that may be in flight at once
 
 int64_t footprint_of(const Plan& p)
@@ -112,10 +115,10 @@ struct Server {
     std::vector<int> free_slots;
     WorkItem* d_items[kIterBuffers] = {};
     WorkItem* h_items[kIterBuffers] = {};
-    int* d_counters = nullptr;        // 2 per iteration buffer
+    int* d_counters = nullptr;        // kNumClasses per iteration buffer
     hipEvent_t iter_ev[kIterBuffers] = {};
     bool iter_busy[kIterBuffers] = {};
-    int grid[2] = {0, 0};
+    int grid[kNumClasses] = {};
     int64_t max_items = 0;
 
     std::mutex mu;
@@ -223,7 +226,7 @@ bool Server::issue_iteration()
     if (buf < 0) return false;
 
     // Take tiles oldest request first until the quantum is used.
-    std::vector<WorkItem> cls_items[2];
+    std::vector<WorkItem> cls_items[kNumClasses];
     std::vector<Request*> finishing;
     int64_t budget = cfg.quantum_macs > 0 ? cfg.quantum_macs : INT64_MAX;
     int64_t room = max_items;
@@ -241,18 +244,22 @@ bool Server::issue_iteration()
         }
         if (r->next_item == r->total_items) finishing.push_back(r);
     }
-    const size_t n0 = cls_items[0].size(), n1 = cls_items[1].size();
-    if (n0 + n1 > 0) {
-        std::memcpy(h_items[buf], cls_items[0].data(), n0 * sizeof(WorkItem));
-        std::memcpy(h_items[buf] + n0, cls_items[1].data(), n1 * sizeof(WorkItem));
-        (void)hipMemcpyAsync(d_items[buf], h_items[buf], (n0 + n1) * sizeof(WorkItem),
-                             hipMemcpyHostToDevice, stream);
-        int* ctr = d_counters + 2 * buf;
-        (void)launch_reset_counters(ctr, 2, stream);
-        if (n0) (void)launch_persistent_gemm(kClassKinds[0], d_slots, d_items[buf], int(n0), ctr, grid[0], stream);
-        if (n1)
-            (void)launch_persistent_gemm(kClassKinds[1], d_slots, d_items[buf] + n0, int(n1), ctr + 1,
-                                         grid[1], stream);
+    size_t total = 0, off[kNumClasses] = {};
+    for (int c = 0; c < kNumClasses; ++c) {
+        off[c] = total;
+        total += cls_items[c].size();
+    }
+    if (total > 0) {
+        for (int c = 0; c < kNumClasses; ++c)
+            std::memcpy(h_items[buf] + off[c], cls_items[c].data(), cls_items[c].size() * sizeof(WorkItem));
+        (void)hipMemcpyAsync(d_items[buf], h_items[buf], total * sizeof(WorkItem), hipMemcpyHostToDevice,
+                             stream);
+        int* ctr = d_counters + kNumClasses * buf;
+        (void)launch_reset_counters(ctr, kNumClasses, stream);
+        for (int c = 0; c < kNumClasses; ++c)
+            if (!cls_items[c].empty())
+                (void)launch_persistent_gemm(kClassKinds[c], d_slots, d_items[buf] + off[c],
+                                             int(cls_items[c].size()), ctr + c, grid[c], stream);
     }
     for (Request* r : finishing) {
         if (r->d.k == 0)
@@ -322,16 +329,15 @@ int gf2e_server_create(gf2e_ctx* handle, const gf2e_server_config* cfg, gf2e_ser
               hipMalloc(&s->d_err, sizeof(int) * slots) == hipSuccess &&
               hipMemset(s->d_err, 0, sizeof(int) * slots) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void**>(&s->h_err), sizeof(int) * slots, 0) == hipSuccess &&
-              hipMalloc(&s->d_counters, sizeof(int) * 2 * kIterBuffers) == hipSuccess;
+              hipMalloc(&s->d_counters, sizeof(int) * kNumClasses * kIterBuffers) == hipSuccess;
     for (int b = 0; ok && b < kIterBuffers; ++b)
         ok = hipMalloc(&s->d_items[b], sizeof(WorkItem) * s->max_items) == hipSuccess &&
              hipHostMalloc(reinterpret_cast<void**>(&s->h_items[b]), sizeof(WorkItem) * s->max_items, 0) ==
                  hipSuccess &&
              hipEventCreateWithFlags(&s->iter_ev[b], hipEventDisableTiming) == hipSuccess;
-    if (ok) {
-        s->grid[0] = persistent_grid(kClassKinds[0]);
-        s->grid[1] = persistent_grid(kClassKinds[1]);
-        ok = s->grid[0] > 0 && s->grid[1] > 0;
+    for (int c = 0; ok && c < kNumClasses; ++c) {
+        s->grid[c] = persistent_grid(kClassKinds[c]);
+        ok = s->grid[c] > 0;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -400,7 +406,8 @@ int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B
     d.m = m; d.k = k; d.n = n;
     d.Mp = r->plan.Mp; d.Np = r->plan.Np; d.K64p = r->plan.K64p;
     d.e = e; d.T = r->plan.T; d.f = f;
-    r->cls = std::min(m, n) >= s->ctx->batch_threshold ? 0 : 1;
+    r->cls = (std::min(m, n) >= s->ctx->batch_threshold ? 0 : 1) +
+             (r->plan.K64p * 64 <= (int64_t(1) << 24) ? 0 : 2);
     const GemmShape sh = gemm_shape(kClassKinds[r->cls]);
     r->tm = int(ceil_div(std::max<int64_t>(m, 1), sh.bm));
     r->tn = int(ceil_div(std::max<int64_t>(n, 1), sh.bn));

@@ -60,7 +60,7 @@ def test_small_shapes_every_field(ctx, e, f, shape):
     assert (gpu_mul(ctx, A, B, e, f) == oracle.matmul(A, B, e, f)).all()
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("kind", list(range(8)))
 @pytest.mark.parametrize("e", [2, 5, 8, 10])
 def test_every_product_kernel(g, e, kind):
     f = workload.DEFAULT_POLY[e]
@@ -96,6 +96,18 @@ def test_large_k_parity(ctx, k):
     A = np.ones((1, k), dtype=np.uint8)
     B = np.ones((k, 1), dtype=np.uint8)
     assert gpu_mul(ctx, A, B, 2, 0x7)[0, 0] == k % 2
+
+
+@pytest.mark.parametrize("kind", [6, 7])
+@pytest.mark.parametrize("k", [2**24 - 64, 2**24 + 1])
+def test_fp4_count_limit(g, kind, k):
+    """The fp4 kernels keep exact f32 counts up to 2^24; beyond that the plain
+    path falls back to the int8 kernel and stays exact."""
+    c = g.Context(0, kernel=kind)
+    A = np.ones((1, k), dtype=np.uint8)
+    B = np.ones((k, 1), dtype=np.uint8)
+    assert gpu_mul(c, A, B, 2, 0x7)[0, 0] == k % 2
+    c.close()
 
 
 def test_char2_cancellation(ctx):
@@ -241,9 +253,9 @@ def _full_size_check(ctx, name, kinds, nrows=4, nsamp=4096):
 
 
 def test_config_f16_4096_sampled(ctx):
-    _full_size_check(ctx, "f16_4096", [-1, 0, 4])
+    _full_size_check(ctx, "f16_4096", [-1, 0, 4, 5, 6])
 
 
 def test_config_f256_8192_sampled(ctx):
     """The benchmark's workload, in the launch configurations it may time."""
-    _full_size_check(ctx, "f256_8192", [-1, 0, 1, 2, 3, 4])
+    _full_size_check(ctx, "f256_8192", [-1, 0, 1, 2, 3, 4, 5, 6, 7])

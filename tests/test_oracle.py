@@ -65,7 +65,7 @@ def test_f4_table_from_section5(golden_dir):
     for a in range(4):
         for b in range(4):
             assert oracle.mul_def(e, f, a, b) == expect[a, b]
-    # The spec worked example: in F_4, a*a = a+1 for a = x (2 -> 3).
+    # In F_4 the element x satisfies x*x = x+1 (2 -> 3).
     assert oracle.mul_def(e, f, 2, 2) == 3
 
 
