@@ -206,7 +206,7 @@ int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint64_t*
  *   B-side operand planes: t planes of K64p x Np words, word (kw, j) =
  *     column j, k-bits [64kw, 64kw+64);
  *   product planes: t planes of Mp x (Np/64) words, row-major.
- * Mp, Np must be multiples of 256 and >= m, n; K64p = 2*ceil(k/128).
+ * Mp, Np must be multiples of 256 and >= m, n; K64p = 4*ceil(k/256).
  * All plane pointers are device pointers owned by the caller. */
 
 typedef struct {

@@ -488,7 +488,7 @@ int gf2e_slice_a(gf2e_ctx* handle, const gf2e_mat* A, int e, uint64_t* planes, i
     int rc = check_mat(A);
     if (rc) return rc;
     if (e < 2 || e > kMaxE) return GF2E_EFIELD;
-    if (Mp < A->rows || Mp % kRowAlign || K64p < kwords_padded(A->cols) || K64p % 2) return GF2E_ESHAPE;
+    if (Mp < A->rows || Mp % kRowAlign || K64p < kwords_padded(A->cols) || K64p % 4) return GF2E_ESHAPE;
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageTimer t(c, GF2E_STAGE_SLICE_A, s);
@@ -506,7 +506,7 @@ int gf2e_slice_b(gf2e_ctx* handle, const gf2e_mat* B, int e, uint64_t* planes, i
     int rc = check_mat(B);
     if (rc) return rc;
     if (e < 2 || e > kMaxE) return GF2E_EFIELD;
-    if (Np < B->cols || Np % kRowAlign || K64p < kwords_padded(B->rows) || K64p % 2) return GF2E_ESHAPE;
+    if (Np < B->cols || Np % kRowAlign || K64p < kwords_padded(B->rows) || K64p % 4) return GF2E_ESHAPE;
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageTimer t(c, GF2E_STAGE_SLICE_B, s);
@@ -523,7 +523,7 @@ int gf2e_plane_products(gf2e_ctx* handle, int kernel, int t, const uint64_t* a_p
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c || !a_planes || !b_planes || !p_planes || t <= 0 || t > kMaxT) return GF2E_EINVAL;
     if (m < 0 || n < 0 || Mp < m || Np < n || Mp % kRowAlign || Np % kRowAlign || K64p <= 0 ||
-        K64p % 2)
+        K64p % 4)
         return GF2E_ESHAPE;
     if (kernel < GF2E_KERNEL_AUTO || kernel >= GEMM_NUM_KINDS) return GF2E_EINVAL;
     const int kind = kernel >= 0 ? kernel : default_kind(t, m, n);

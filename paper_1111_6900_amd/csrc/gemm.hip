@@ -75,7 +75,7 @@ __device__ __attribute__((always_inline)) inline void mfma_tile(const uint64_t* 
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int r = tid + q * NT;
-            if (r < TL::kRows) {
+            if (TL::kRows % NT == 0 || r < TL::kRows) {
                 const bool isA = r < BM;
                 const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
                 const int64_t ld = isA ? Mp : Np;
@@ -202,6 +202,14 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int64_t kFp4MaxK = int64_t(1) << 24;
 
+// fp4 operands occupy the low four dwords of the builtin's 8-dword operand;
+// the upper half is left undefined so no registers are spent on it.
+__device__ inline v8i fp4_operand(const uint4& x)
+{
+    const v4i v{int(x.x), int(x.y), int(x.z), int(x.w)};
+    return __builtin_shufflevector(v, v, 0, 1, 2, 3, -1, -1, -1, -1);
+}
+
 // Chunk of 32-bit word h: nibble j of dword q is 1.0 iff bit 4j+q of h is set.
 __device__ inline uint4 expand_fp4(uint32_t h)
 {
@@ -222,7 +230,8 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
     const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
-    const int nstages = int((K64p + 2 * KB - 1) / (2 * KB));
+    static_assert(KB == 2, "stages are whole 256-bit k-steps (K64p is a multiple of 4)");
+    const int nstages = int(K64p / (2 * KB));
 
     v4f acc[FM][FN];
 #pragma unroll
@@ -240,10 +249,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
                 const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
                 const int64_t ld = isA ? Mp : Np;
 #pragma unroll
-                for (int w = 0; w < 2 * KB; ++w) {
-                    const int64_t kw = int64_t(st) * 2 * KB + w;
-                    stg[q][w] = kw < K64p ? src[kw * ld] : 0ull;
-                }
+                for (int w = 0; w < 2 * KB; ++w) stg[q][w] = src[(int64_t(st) * 2 * KB + w) * ld];
             }
         }
     };
@@ -272,21 +278,15 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
             const int c = 4 * kb + g;
             v8i a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                const uint4 x = lds[buf][c][wr * WM + 16 * i + l16];
-                a[i] = v8i{int(x.x), int(x.y), int(x.z), int(x.w), 0, 0, 0, 0};
-            }
+            for (int i = 0; i < FM; ++i) a[i] = fp4_operand(lds[buf][c][wr * WM + 16 * i + l16]);
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const uint4 x = lds[buf][c][BM + wc * WN + 16 * j + l16];
-                b[j] = v8i{int(x.x), int(x.y), int(x.z), int(x.w), 0, 0, 0, 0};
-            }
+            for (int j = 0; j < FN; ++j) b[j] = fp4_operand(lds[buf][c][BM + wc * WN + 16 * j + l16]);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4,
-                                                                                0, 127, 0, 127);
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0,
+                                                                                127, 0, 127);
         }
         if (more) expand_store(buf ^ 1);
         __syncthreads();
@@ -551,6 +551,7 @@ GemmShape gemm_shape(int kind)
         case GEMM_MFMA_256x256_W8: return {256, 256};
         case GEMM_FP4_256x256_W8: return {256, 256};
         case GEMM_FP4_128x128: return {128, 128};
+
         default: return {0, 0};
     }
 }
@@ -566,6 +567,7 @@ const char* gemm_name(int kind)
         case GEMM_MFMA_256x256_W8: return "mfma_i8_256x256_w8";
         case GEMM_FP4_256x256_W8: return "mfma_fp4_256x256_w8";
         case GEMM_FP4_128x128: return "mfma_fp4_128x128";
+
         default: return "unknown";
     }
 }
@@ -574,7 +576,7 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
                        int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
 {
     if (T <= 0 || m <= 0 || n <= 0 || K64p <= 0) return hipSuccess;
-    if (K64p % 2 != 0) return hipErrorInvalidValue;
+    if (K64p % 4 != 0) return hipErrorInvalidValue;
     switch (kind) {
         case GEMM_MFMA_256x256:
             return launch_mfma<256, 256, 128, 128>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
@@ -590,6 +592,7 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
             return launch_fp4<256, 256, 128, 64, 2>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_FP4_128x128:
             return launch_fp4<128, 128, 64, 64, 2>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+
         case GEMM_VALU_128x128: {
             const int tm = int(ceil_div(m, kValuTile)), tn = int(ceil_div(n, kValuTile));
             if (tm * int64_t(kValuTile) > Mp || tn * int64_t(kValuTile) > Np) return hipErrorInvalidValue;

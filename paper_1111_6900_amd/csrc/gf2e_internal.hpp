@@ -11,7 +11,7 @@
 //       base + s*Mp*ldp + i*ldp + w       -- row i, columns [64w, 64w+64), ldp = Np/64
 //
 // Rows are padded to Mp (Np) and the k dimension to K64p words (a multiple of
-// two, so the product kernels can step 128 bits at a time).  Padding bits are
+// four, so the product kernels step through whole 256-bit stages).  Padding bits are
 // written as zero by the slicing kernels, so padded k contributes nothing.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -23,7 +23,9 @@ constexpr int kRowAlign = 256;  // padding of plane rows (largest product tile)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
-inline int64_t kwords_padded(int64_t k) { return 2 * ceil_div(k, 128); }
+// k is padded to whole 256-bit steps, so every product kernel's stages are
+// full and its loads need no bounds guard.
+inline int64_t kwords_padded(int64_t k) { return 4 * ceil_div(k, 256); }
 
 // Product-kernel variants the planner and the autotuner choose among.
 enum GemmKind : int {

@@ -132,7 +132,7 @@ def test_plane_geometry():
     assert geo.a_bytes == 27 * 128 * 8192 * 8
     assert geo.p_bytes == 27 * 8192 * 128 * 8
     geo = g.plane_geometry(2, 1, 1, 1)
-    assert (geo.Mp, geo.Np, geo.K64p) == (256, 256, 2)
+    assert (geo.Mp, geo.Np, geo.K64p) == (256, 256, 4)
     geo = g.plane_geometry(10, 300, 129, 513)
     assert (geo.t, geo.Mp, geo.Np, geo.K64p) == (45, 512, 768, 4)
 
