@@ -135,7 +135,7 @@ def batched_leg(g, torch, workload, log, reps=5):
     ctx.sync()
     info = ctx.batch_info()
     emacs = sum(m * k * n for (_, _, m, k, n) in specs)
-    bmacs = sum(g.num_products(e) * m * k * n for (e, _, m, k, n) in specs)
+    bmacs = sum(g.num_products(e, f) * m * k * n for (e, f, m, k, n) in specs)
     ctx.close()
     return {"products": len(specs), "element_macs": emacs, "bit_macs": bmacs,
             "plain_ms": round(plain_ms, 4), "batched_ms": round(batched_ms, 4),
@@ -251,7 +251,7 @@ def main():
     for _ in range(args.warmup):
         ctx.mul_async(Ad, Bd, e, f, out=C)
     ctx.sync()
-    kind = ctx.chosen_kernel(e, m, k, n)
+    kind = ctx.chosen_kernel(e, f, m, k, n)
     log(args, f"product kernel: {g.kernel_names()[kind]}")
 
     ctx.profile(True)
@@ -272,7 +272,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = m * k * n / (ms_per_step / 1e3)
 
-    T = g.num_products(e)
+    T = g.num_products(e, f)
     prod_ms = stages["products"]
     kname = g.kernel_names()[kind]
     bound, peak, unit, ops_per_mac = kernel_roofline(kname)

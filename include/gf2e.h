@@ -188,14 +188,18 @@ const char* gf2e_strerror(int code);
 /* GF2E_OK when 2 <= e <= 10 and f is irreducible of degree e. */
 int gf2e_field_check(int e, uint32_t f);
 
-/* Number t(e) of GF(2) products in the Karatsuba schedule, or < 0. */
-int gf2e_num_products(int e);
+/* Number t of GF(2) products in the schedule used for (e, f), or < 0. */
+int gf2e_num_products(int e, uint32_t f);
 
-/* The schedule of Section 5 for (e, f): product s multiplies
- * (XOR_{i in u[s]} A_i) by (XOR_{j in v[s]} B_j); coefficient d of the
- * polynomial product is XOR_{s in w[d]} P_s (d < 2e-1); plane c of the
- * reduced result is XOR_{s in m[c]} P_s (c < e).  Arrays: u, v of length
- * >= t, w of length >= 2e-1, m of length >= e; any may be NULL. */
+/* The product schedule used for (e, f): product s multiplies
+ * (XOR_{i in u[s]} A_i) by (XOR_{j in v[s]} B_j); plane c of the reduced
+ * result is XOR_{s in m[c]} P_s (c < e).  For the Karatsuba schedule of
+ * Section 5, coefficient d of the polynomial product is XOR_{s in w[d]} P_s
+ * (d < 2e-1) before reduction modulo f; for a schedule compiled in for this
+ * particular f (fewer products, reduction folded in) w is all zero.  Arrays:
+ * u, v of length >= t, w of length >= 2e-1, m of length >= e; any may be
+ * NULL.  GF2E_SCHEDULE=karatsuba in the environment selects Karatsuba for
+ * every field. */
 int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint64_t* w,
                   uint64_t* m);
 
@@ -216,14 +220,14 @@ typedef struct {
     int64_t a_bytes, b_bytes, p_bytes; /* sizes of the three plane buffers */
 } gf2e_geometry;
 
-int gf2e_plane_geometry(int e, int64_t m, int64_t k, int64_t n, gf2e_geometry* g);
+int gf2e_plane_geometry(int e, uint32_t f, int64_t m, int64_t k, int64_t n, gf2e_geometry* g);
 
-/* Slice A (m x k) into the t Karatsuba operand planes of the A side
- * (Section 3.2 slicing fused with the operand sums of Section 5). */
-int gf2e_slice_a(gf2e_ctx* ctx, const gf2e_mat* A, int e, uint64_t* planes, int64_t Mp,
+/* Slice A (m x k) into the t operand planes of the A side of the (e, f)
+ * schedule (Section 3.2 slicing fused with the operand sums of Section 5). */
+int gf2e_slice_a(gf2e_ctx* ctx, const gf2e_mat* A, int e, uint32_t f, uint64_t* planes, int64_t Mp,
                  int64_t K64p, void* stream);
 /* Slice B (k x n) column-wise into the t transposed operand planes. */
-int gf2e_slice_b(gf2e_ctx* ctx, const gf2e_mat* B, int e, uint64_t* planes, int64_t Np,
+int gf2e_slice_b(gf2e_ctx* ctx, const gf2e_mat* B, int e, uint32_t f, uint64_t* planes, int64_t Np,
                  int64_t K64p, void* stream);
 /* P_s = Ahat_s * Bhat_s^T over GF(2) for s < t, one grouped launch of the
  * given kernel (GF2E_KERNEL_*, AUTO allowed). */
@@ -239,10 +243,10 @@ int gf2e_combine(gf2e_ctx* ctx, int e, uint32_t f, const uint64_t* p_planes, int
 int gf2e_kernel_count(void);
 const char* gf2e_kernel_name(int kernel);
 int gf2e_set_kernel(gf2e_ctx* ctx, int kernel);
-/* Kernel the planner would use now for an (e, m, k, n) product. */
-int gf2e_chosen_kernel(gf2e_ctx* ctx, int e, int64_t m, int64_t k, int64_t n);
+/* Kernel the planner would use now for an (e, f, m, k, n) product. */
+int gf2e_chosen_kernel(gf2e_ctx* ctx, int e, uint32_t f, int64_t m, int64_t k, int64_t n);
 /* Time every candidate kernel for this shape now and cache the fastest. */
-int gf2e_tune(gf2e_ctx* ctx, int e, int64_t m, int64_t k, int64_t n, void* stream);
+int gf2e_tune(gf2e_ctx* ctx, int e, uint32_t f, int64_t m, int64_t k, int64_t n, void* stream);
 
 /* Stage timers: when enabled, every launch of a stage is bracketed by HIP
  * events on the stream it runs on.  Stages: 0 slice A, 1 slice B,

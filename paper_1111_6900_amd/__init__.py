@@ -93,18 +93,18 @@ _SIGS = {
     "gf2e_server_run_trace": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_strerror": (ctypes.c_char_p, [_i32]),
     "gf2e_field_check": (_i32, [_i32, _u32]),
-    "gf2e_num_products": (_i32, [_i32]),
+    "gf2e_num_products": (_i32, [_i32, _u32]),
     "gf2e_schedule": (_i32, [_i32, _u32, _P(_i32), _vp, _vp, _vp, _vp]),
-    "gf2e_plane_geometry": (_i32, [_i32, _i64, _i64, _i64, _P(Geometry)]),
-    "gf2e_slice_a": (_i32, [_vp, _P(Mat), _i32, _vp, _i64, _i64, _vp]),
-    "gf2e_slice_b": (_i32, [_vp, _P(Mat), _i32, _vp, _i64, _i64, _vp]),
+    "gf2e_plane_geometry": (_i32, [_i32, _u32, _i64, _i64, _i64, _P(Geometry)]),
+    "gf2e_slice_a": (_i32, [_vp, _P(Mat), _i32, _u32, _vp, _i64, _i64, _vp]),
+    "gf2e_slice_b": (_i32, [_vp, _P(Mat), _i32, _u32, _vp, _i64, _i64, _vp]),
     "gf2e_plane_products": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp]),
     "gf2e_combine": (_i32, [_vp, _i32, _u32, _vp, _i64, _i64, _P(Mat), _vp]),
     "gf2e_kernel_count": (_i32, []),
     "gf2e_kernel_name": (ctypes.c_char_p, [_i32]),
     "gf2e_set_kernel": (_i32, [_vp, _i32]),
-    "gf2e_chosen_kernel": (_i32, [_vp, _i32, _i64, _i64, _i64]),
-    "gf2e_tune": (_i32, [_vp, _i32, _i64, _i64, _i64, _vp]),
+    "gf2e_chosen_kernel": (_i32, [_vp, _i32, _u32, _i64, _i64, _i64]),
+    "gf2e_tune": (_i32, [_vp, _i32, _u32, _i64, _i64, _i64, _vp]),
     "gf2e_profile": (_i32, [_vp, _i32]),
     "gf2e_profile_read": (_i32, [_vp, _i32, _P(ctypes.c_double), _P(_i64)]),
     "gf2e_profile_reset": (_i32, [_vp]),
@@ -150,16 +150,18 @@ def field_check(e: int, f: int) -> bool:
     return lib().gf2e_field_check(e, f) == OK
 
 
-def num_products(e: int) -> int:
-    rc = lib().gf2e_num_products(e)
+def num_products(e: int, f: int) -> int:
+    """GF(2) products in the schedule used for F_2[x]/<f>."""
+    rc = lib().gf2e_num_products(e, f)
     if rc < 0:
         raise GF2EError(rc, "num_products")
     return rc
 
 
 def schedule(e: int, f: int) -> dict:
-    """The Section 5 schedule: u, v (operand subsets), w (polynomial
-    recombination) and m (recombination after reduction mod f)."""
+    """The product schedule used for (e, f): u, v (operand subsets), w
+    (polynomial recombination; all zero when the schedule has the reduction
+    folded in) and m (result planes after reduction mod f)."""
     t = ctypes.c_int(0)
     u = (ctypes.c_uint32 * 64)()
     v = (ctypes.c_uint32 * 64)()
@@ -170,9 +172,9 @@ def schedule(e: int, f: int) -> dict:
     return {"t": T, "u": list(u[:T]), "v": list(v[:T]), "w": list(w[:2 * e - 1]), "m": list(m[:e])}
 
 
-def plane_geometry(e: int, m: int, k: int, n: int) -> Geometry:
+def plane_geometry(e: int, f: int, m: int, k: int, n: int) -> Geometry:
     g = Geometry()
-    _check(lib().gf2e_plane_geometry(e, m, k, n, ctypes.byref(g)), "plane_geometry")
+    _check(lib().gf2e_plane_geometry(e, f, m, k, n, ctypes.byref(g)), "plane_geometry")
     return g
 
 
@@ -303,14 +305,14 @@ class Context:
         return {k: getattr(st, k) for k, _ in BatchStats._fields_}
 
     # -- stages --------------------------------------------------------------
-    def slice_a(self, A, e, planes, Mp, K64p, stream=None):
+    def slice_a(self, A, e, f, planes, Mp, K64p, stream=None):
         a = mat(A)
-        _check(lib().gf2e_slice_a(self.handle, ctypes.byref(a), e, ctypes.c_void_p(planes.data_ptr()),
+        _check(lib().gf2e_slice_a(self.handle, ctypes.byref(a), e, f, ctypes.c_void_p(planes.data_ptr()),
                                   Mp, K64p, _stream_handle(stream)), "gf2e_slice_a")
 
-    def slice_b(self, B, e, planes, Np, K64p, stream=None):
+    def slice_b(self, B, e, f, planes, Np, K64p, stream=None):
         b = mat(B)
-        _check(lib().gf2e_slice_b(self.handle, ctypes.byref(b), e, ctypes.c_void_p(planes.data_ptr()),
+        _check(lib().gf2e_slice_b(self.handle, ctypes.byref(b), e, f, ctypes.c_void_p(planes.data_ptr()),
                                   Np, K64p, _stream_handle(stream)), "gf2e_slice_b")
 
     def plane_products(self, kernel, t, a_planes, b_planes, p_planes, m, n, Mp, Np, K64p,
@@ -329,14 +331,14 @@ class Context:
     def set_kernel(self, kernel: int):
         _check(lib().gf2e_set_kernel(self.handle, kernel), "gf2e_set_kernel")
 
-    def chosen_kernel(self, e, m, k, n) -> int:
-        rc = lib().gf2e_chosen_kernel(self.handle, e, m, k, n)
+    def chosen_kernel(self, e, f, m, k, n) -> int:
+        rc = lib().gf2e_chosen_kernel(self.handle, e, f, m, k, n)
         if rc < 0:
             raise GF2EError(rc, "gf2e_chosen_kernel")
         return rc
 
-    def tune(self, e, m, k, n, stream=None):
-        _check(lib().gf2e_tune(self.handle, e, m, k, n, _stream_handle(stream)), "gf2e_tune")
+    def tune(self, e, f, m, k, n, stream=None):
+        _check(lib().gf2e_tune(self.handle, e, f, m, k, n, _stream_handle(stream)), "gf2e_tune")
 
     def profile(self, enable: bool = True):
         _check(lib().gf2e_profile(self.handle, 1 if enable else 0), "gf2e_profile")

@@ -25,14 +25,20 @@ FLAGS = [
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    # the compiler's per-kernel register / scratch / LDS report is kept next to
+    # the object (tests check that no kernel spills to scratch)
+    cmd = [HIPCC, *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass does not know the disabled target feature; drop that note
-    noise = [l for l in (res.stderr or "").splitlines() if "packed-fp32-ops" not in l]
+    lines = [l for l in (res.stderr or "").splitlines() if "packed-fp32-ops" not in l]
+    remarks = [l for l in lines if "kernel-resource-usage" in l]
+    noise = [l for l in lines if "kernel-resource-usage" not in l]
     if res.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n" + "\n".join(noise))
+    with open(obj + ".resources.txt", "w") as fh:
+        fh.write("\n".join(remarks) + "\n")
     if verbose and noise:
         print("\n".join(noise), file=sys.stderr)
     return obj

@@ -71,11 +71,22 @@ int validate_mul(const gf2e_mat* A, const gf2e_mat* B, const gf2e_mat* C, int e,
     return GF2E_OK;
 }
 
-Plan make_plan(int e, int64_t m, int64_t k, int64_t n)
+int schedule_id(int e, uint32_t f)
+{
+    static const bool karatsuba_only = [] {
+        const char* v = std::getenv("GF2E_SCHEDULE");
+        return v && std::strcmp(v, "karatsuba") == 0;
+    }();
+    return karatsuba_only ? -1 : find_field_schedule(e, f);
+}
+
+Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n)
 {
     Plan p{};
     p.e = e;
-    p.T = best_count(e);
+    p.f = f;
+    p.sid = schedule_id(e, f);
+    p.T = p.sid >= 0 ? kFieldSchedules[p.sid].t : best_count(e);
     p.m = m; p.k = k; p.n = n;
     p.Mp = round_up(std::max<int64_t>(m, 1), kRowAlign);
     p.Np = round_up(std::max<int64_t>(n, 1), kRowAlign);
@@ -282,12 +293,12 @@ int Ctx::run_plan(const Plan& p, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat*
     hipError_t err;
     {
         StageTimer t(this, GF2E_STAGE_SLICE_A, s);
-        err = launch_slice_rows(p.e, A->data, A->ld, p.m, p.k, Apl, p.Mp, p.K64p, d_err, s);
+        err = launch_slice_rows(p.e, p.sid, A->data, A->ld, p.m, p.k, Apl, p.Mp, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
         StageTimer t(this, GF2E_STAGE_SLICE_B, s);
-        err = launch_slice_cols(p.e, B->data, B->ld, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s);
+        err = launch_slice_cols(p.e, p.sid, B->data, B->ld, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
@@ -297,7 +308,7 @@ int Ctx::run_plan(const Plan& p, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat*
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
         StageTimer t(this, GF2E_STAGE_COMBINE, s);
-        err = launch_combine(p.e, f, P, p.Mp, p.Np / 64, p.m, p.n, C->data, C->ld, s);
+        err = launch_combine(p.e, p.sid, f, P, p.Mp, p.Np / 64, p.m, p.n, C->data, C->ld, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     return GF2E_OK;
@@ -331,40 +342,46 @@ const char* gf2e_strerror(int code)
 
 int gf2e_field_check(int e, uint32_t f) { return field_ok(e, f) ? GF2E_OK : GF2E_EFIELD; }
 
-int gf2e_num_products(int e)
+int gf2e_num_products(int e, uint32_t f)
 {
-    if (e < 2 || e > kMaxE) return GF2E_EFIELD;
-    return best_count(e);
+    if (!field_ok(e, f)) return GF2E_EFIELD;
+    return make_plan(e, f, 1, 1, 1).T;
 }
 
 int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint64_t* w, uint64_t* m)
 {
     if (!field_ok(e, f)) return GF2E_EFIELD;
-    const Schedule S = build_schedule(e);
+    const KernelSchedule S = kernel_schedule(e, schedule_id(e, f));
     if (t) *t = S.t;
     for (int s = 0; s < S.t; ++s) {
         if (u) u[s] = S.u[s];
         if (v) v[s] = S.v[s];
     }
     for (int d = 0; d < 2 * e - 1; ++d)
-        if (w) w[d] = S.w[d];
+        if (w) w[d] = S.w[d];  // zero for a field schedule (reduction folded in)
     if (m) {
         for (int c = 0; c < e; ++c) m[c] = 0;
-        for (int d = 0; d < 2 * e - 1; ++d) {
-            const uint32_t col = x_pow_mod(d, f, e);
-            for (int c = 0; c < e; ++c)
-                if ((col >> c) & 1u) m[c] ^= S.w[d];
+        if (S.folded) {
+            for (int s = 0; s < S.t; ++s)
+                for (int c = 0; c < e; ++c)
+                    if ((S.c[s] >> c) & 1u) m[c] |= uint64_t(1) << s;
+        } else {
+            for (int d = 0; d < 2 * e - 1; ++d) {
+                const uint32_t col = x_pow_mod(d, f, e);
+                for (int c = 0; c < e; ++c)
+                    if ((col >> c) & 1u) m[c] ^= S.w[d];
+            }
         }
     }
     return GF2E_OK;
 }
 
-int gf2e_plane_geometry(int e, int64_t m, int64_t k, int64_t n, gf2e_geometry* g)
+int gf2e_plane_geometry(int e, uint32_t f, int64_t m, int64_t k, int64_t n, gf2e_geometry* g)
 {
     if (!g) return GF2E_EINVAL;
-    if (e < 2 || e > kMaxE) return GF2E_EFIELD;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
     if (m < 0 || k < 0 || n < 0) return GF2E_ESHAPE;
-    const Plan p = make_plan(e, m, k, n);
+    const Plan p = make_plan(e, f, m, k, n);
     g->t = p.T;
     g->Mp = p.Mp;
     g->Np = p.Np;
@@ -449,7 +466,7 @@ int gf2e_mul_async(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_
         c->mark_used(s);
         return GF2E_OK;
     }
-    const Plan p = make_plan(e, m, k, n);
+    const Plan p = make_plan(e, f, m, k, n);
     rc = c->run_plan(p, A, B, C, f, s);
     c->mark_used(s);
     return rc;
@@ -480,37 +497,39 @@ int gf2e_mul(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C
     return gf2e_sync(handle, nullptr);
 }
 
-int gf2e_slice_a(gf2e_ctx* handle, const gf2e_mat* A, int e, uint64_t* planes, int64_t Mp,
+int gf2e_slice_a(gf2e_ctx* handle, const gf2e_mat* A, int e, uint32_t f, uint64_t* planes, int64_t Mp,
                  int64_t K64p, void* stream)
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c || !planes) return GF2E_EINVAL;
     int rc = check_mat(A);
     if (rc) return rc;
-    if (e < 2 || e > kMaxE) return GF2E_EFIELD;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
     if (Mp < A->rows || Mp % kRowAlign || K64p < kwords_padded(A->cols) || K64p % 4) return GF2E_ESHAPE;
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageTimer t(c, GF2E_STAGE_SLICE_A, s);
-    return launch_slice_rows(e, A->data, A->ld, A->rows, A->cols, planes, Mp, K64p, c->d_err, s) ==
+    return launch_slice_rows(e, schedule_id(e, f), A->data, A->ld, A->rows, A->cols, planes, Mp, K64p,
+                             c->d_err, s) ==
                    hipSuccess
                ? GF2E_OK
                : GF2E_EDEVICE;
 }
 
-int gf2e_slice_b(gf2e_ctx* handle, const gf2e_mat* B, int e, uint64_t* planes, int64_t Np,
+int gf2e_slice_b(gf2e_ctx* handle, const gf2e_mat* B, int e, uint32_t f, uint64_t* planes, int64_t Np,
                  int64_t K64p, void* stream)
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c || !planes) return GF2E_EINVAL;
     int rc = check_mat(B);
     if (rc) return rc;
-    if (e < 2 || e > kMaxE) return GF2E_EFIELD;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
     if (Np < B->cols || Np % kRowAlign || K64p < kwords_padded(B->rows) || K64p % 4) return GF2E_ESHAPE;
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageTimer t(c, GF2E_STAGE_SLICE_B, s);
-    return launch_slice_cols(e, B->data, B->ld, B->rows, B->cols, planes, Np, K64p, c->d_err, s) ==
+    return launch_slice_cols(e, schedule_id(e, f), B->data, B->ld, B->rows, B->cols, planes, Np, K64p,
+                             c->d_err, s) ==
                    hipSuccess
                ? GF2E_OK
                : GF2E_EDEVICE;
@@ -547,7 +566,8 @@ int gf2e_combine(gf2e_ctx* handle, int e, uint32_t f, const uint64_t* p_planes, 
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageTimer t(c, GF2E_STAGE_COMBINE, s);
-    return launch_combine(e, f, p_planes, Mp, Np / 64, C->rows, C->cols, C->data, C->ld, s) ==
+    return launch_combine(e, schedule_id(e, f), f, p_planes, Mp, Np / 64, C->rows, C->cols, C->data, C->ld,
+                          s) ==
                    hipSuccess
                ? GF2E_OK
                : GF2E_EDEVICE;
@@ -565,24 +585,24 @@ int gf2e_set_kernel(gf2e_ctx* handle, int kernel)
     return GF2E_OK;
 }
 
-int gf2e_chosen_kernel(gf2e_ctx* handle, int e, int64_t m, int64_t k, int64_t n)
+int gf2e_chosen_kernel(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k, int64_t n)
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c) return GF2E_EINVAL;
-    if (e < 2 || e > kMaxE) return GF2E_EFIELD;
-    return c->choose_kind(make_plan(e, m, k, n));
+    if (!field_ok(e, f)) return GF2E_EFIELD;
+    return c->choose_kind(make_plan(e, f, m, k, n));
 }
 
-int gf2e_tune(gf2e_ctx* handle, int e, int64_t m, int64_t k, int64_t n, void* stream)
+int gf2e_tune(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k, int64_t n, void* stream)
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c) return GF2E_EINVAL;
-    if (e < 2 || e > kMaxE) return GF2E_EFIELD;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
     if (m <= 0 || k <= 0 || n <= 0) return GF2E_ESHAPE;
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     c->order_stream(s);
-    int rc = c->tune_now(make_plan(e, m, k, n), s);
+    int rc = c->tune_now(make_plan(e, f, m, k, n), s);
     c->mark_used(s);
     return rc;
 }

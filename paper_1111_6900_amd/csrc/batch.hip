@@ -91,13 +91,13 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
     for (int p = 0; p < count; ++p) {
         const int64_t m = A[p].rows, k = A[p].cols, n = B[p].cols;
         if (m == 0 || n == 0) continue;
-        const Plan pl = make_plan(e[p], m, k, n);
+        const Plan pl = make_plan(e[p], f[p], m, k, n);
         BatchProduct d{};
         d.A = A[p].data; d.B = B[p].data; d.C = C[p].data;
         d.lda = A[p].ld; d.ldb = B[p].ld; d.ldc = C[p].ld;
         d.m = m; d.k = k; d.n = n;
         d.Mp = pl.Mp; d.Np = pl.Np; d.K64p = pl.K64p;
-        d.e = e[p]; d.T = pl.T; d.f = f[p];
+        d.e = e[p]; d.T = pl.T; d.f = f[p]; d.sid = pl.sid;
         d.slice_a_blocks = k > 0 ? int32_t(pl.Mp / TPB * pl.K64p) : 0;
         d.slice_b_blocks = k > 0 ? int32_t(pl.Np / TPB * pl.K64p) : 0;
         d.combine_blocks = int32_t(ceil_div(m * ceil_div(n, 64), TPB));
@@ -118,7 +118,7 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
         BatchProduct& d = prods[i];
         if (d.k == 0) continue;
         uint8_t* base = static_cast<uint8_t*>(bg->arena) + offs[i];
-        const Plan pl = make_plan(d.e, d.m, d.k, d.n);
+        const Plan pl = make_plan(d.e, d.f, d.m, d.k, d.n);
         d.Apl = reinterpret_cast<uint64_t*>(base);
         d.Bpl = reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes));
         d.P = reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes) + align256(pl.b_bytes));

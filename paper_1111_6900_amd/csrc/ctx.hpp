@@ -26,6 +26,8 @@ private:
 // Sizes of one product's planes (see the layout notes in gf2e_internal.hpp).
 struct Plan {
     int e = 0, T = 0;
+    int sid = -1;  // schedule: < 0 Karatsuba + run-time reduction, else field schedule
+    uint32_t f = 0;
     int64_t m = 0, k = 0, n = 0;
     int64_t Mp = 0, Np = 0, K64p = 0;
     int64_t a_bytes = 0, b_bytes = 0, p_bytes = 0;
@@ -36,7 +38,10 @@ bool field_ok(int e, uint32_t f);
 int check_mat(const gf2e_mat* M);
 bool overlaps(const gf2e_mat* X, const gf2e_mat* Y, int esz);
 int validate_mul(const gf2e_mat* A, const gf2e_mat* B, const gf2e_mat* C, int e, uint32_t f);
-Plan make_plan(int e, int64_t m, int64_t k, int64_t n);
+// Schedule for (e, f): the field schedule if one is compiled in (and not
+// disabled with GF2E_SCHEDULE=karatsuba), else -1.
+int schedule_id(int e, uint32_t f);
+Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n);
 int default_kind(int T, int64_t m, int64_t n);
 bool kind_supports(int kind, const Plan& p);
 

@@ -171,7 +171,7 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        const int it = __builtin_amdgcn_readfirstlane(next);  // uniform: item fields go to SGPRs
         __syncthreads();
         if (it >= nitems) break;
         const WorkItem w = items[it];
@@ -332,7 +332,7 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_fp4
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = next;
+        const int it = __builtin_amdgcn_readfirstlane(next);  // uniform: item fields go to SGPRs
         __syncthreads();
         if (it >= nitems) break;
         const WorkItem w = items[it];

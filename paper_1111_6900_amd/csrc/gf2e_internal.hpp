@@ -46,21 +46,25 @@ struct GemmShape {
 GemmShape gemm_shape(int kind);
 const char* gemm_name(int kind);
 
-// Slice rows of A (m x k elements) into T Karatsuba operand planes.
-hipError_t launch_slice_rows(int e, const void* A, int64_t lda, int64_t m, int64_t k,
+// The kernels of one product run the schedule (e, sid): sid < 0 is the
+// Karatsuba schedule for e (reduction mod f at run time), sid >= 0 the field
+// schedule kFieldSchedules[sid] (see gf2e_schedule.hpp).
+
+// Slice rows of A (m x k elements) into the schedule's A-side operand planes.
+hipError_t launch_slice_rows(int e, int sid, const void* A, int64_t lda, int64_t m, int64_t k,
                              uint64_t* planes, int64_t Mp, int64_t K64p, int* err,
                              hipStream_t s);
-// Slice columns of B (k x n elements) into T transposed operand planes.
-hipError_t launch_slice_cols(int e, const void* B, int64_t ldb, int64_t k, int64_t n,
+// Slice columns of B (k x n elements) into its transposed B-side planes.
+hipError_t launch_slice_cols(int e, int sid, const void* B, int64_t ldb, int64_t k, int64_t n,
                              uint64_t* planes, int64_t Np, int64_t K64p, int* err,
                              hipStream_t s);
 // T plane products P_s = Ahat_s * Bhat_s^T over GF(2), one grouped launch.
 hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P,
                        int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t K64p,
                        hipStream_t s);
-// Recombine the T products into 2e-1 coefficient planes, reduce mod f, and
-// write C (m x n elements).
-hipError_t launch_combine(int e, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
+// Recombine the T products into result planes (reducing mod f for Karatsuba
+// schedules) and write C (m x n elements).
+hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
                           int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s);
 // One product of a batch, as the batched kernels read it from device memory.
 struct BatchProduct {
@@ -75,6 +79,7 @@ struct BatchProduct {
     uint64_t* P;
     int32_t e, T;
     uint32_t f;
+    int32_t sid;  // schedule: < 0 Karatsuba, else field schedule index
     int32_t slice_a_blocks;  // 256-thread jobs of A-side slicing (0 when k = 0)
     int32_t slice_b_blocks;
     int32_t combine_blocks;

@@ -187,3 +187,56 @@ constexpr Schedule build_schedule(int n)
 constexpr int num_products(int e) { return best_count(e); }
 
 }  // namespace gf2e
+
+#include "gf2e_field_schedules.hpp"
+
+namespace gf2e {
+
+// The schedule a set of kernels runs.  sid < 0: the Karatsuba schedule for
+// e, whose 2e-1 coefficient planes w are reduced modulo f at run time.
+// sid >= 0: kFieldSchedules[sid], a schedule for one field with the reduction
+// folded in, so that result plane c is the XOR of the products s with c in
+// c[s].  u and v are the operand subsets of the A and B sides.
+struct KernelSchedule {
+    int e = 0;
+    int t = 0;
+    bool folded = false;
+    uint32_t u[kMaxT] = {}, v[kMaxT] = {}, c[kMaxT] = {};
+    uint64_t w[kMaxD] = {};
+};
+
+constexpr KernelSchedule kernel_schedule(int e, int sid)
+{
+    KernelSchedule k{};
+    if (sid < 0) {
+        const Schedule S = build_schedule(e);
+        k.e = e;
+        k.t = S.t;
+        for (int s = 0; s < S.t; ++s) {
+            k.u[s] = S.u[s];
+            k.v[s] = S.v[s];
+        }
+        for (int d = 0; d < 2 * e - 1; ++d) k.w[d] = S.w[d];
+    } else {
+        const FieldSchedule& F = kFieldSchedules[sid];
+        k.e = F.e;
+        k.t = F.t;
+        k.folded = true;
+        for (int s = 0; s < F.t; ++s) {
+            k.u[s] = F.a[s];
+            k.v[s] = F.b[s];
+            k.c[s] = F.c[s];
+        }
+    }
+    return k;
+}
+
+// Index of the field schedule for (e, f), or -1 (use Karatsuba + reduction).
+constexpr int find_field_schedule(int e, uint32_t f)
+{
+    for (int i = 0; i < kNumFieldSchedules; ++i)
+        if (kFieldSchedules[i].e == e && kFieldSchedules[i].f == f) return i;
+    return -1;
+}
+
+}  // namespace gf2e

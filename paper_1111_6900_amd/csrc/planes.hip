@@ -44,24 +44,26 @@ __device__ inline void bytes_to_planes(const uint64_t (&lo)[8], const uint64_t (
     }
 }
 
-// Karatsuba operand planes: out[s] = XOR of planes[i] for i in u[s].
-template <int E>
+// Operand planes of the schedule: out[s] = XOR of planes[i] for i in u[s]
+// (A side) or v[s] (B side).
+template <int E, int SID, bool BSIDE>
 __device__ inline void store_operands(const uint64_t (&planes)[E], uint64_t* dst,
                                       int64_t plane_stride)
 {
-    constexpr Schedule S = build_schedule(E);
+    constexpr KernelSchedule S = kernel_schedule(E, SID);
+    static_assert(S.e == E, "schedule and field size differ");
 #pragma unroll
     for (int s = 0; s < S.t; ++s) {
         uint64_t w = 0;
 #pragma unroll
         for (int i = 0; i < E; ++i)
-            if ((S.u[s] >> i) & 1u) w ^= planes[i];
+            if (((BSIDE ? S.v[s] : S.u[s]) >> i) & 1u) w ^= planes[i];
         dst[s * plane_stride] = w;
     }
 }
 
 // Row slicing of one plane word: row r of A, k-bits [64kw, 64kw+64).
-template <int E>
+template <int E, int SID>
 __device__ __attribute__((always_inline)) inline void slice_row_word(const void* __restrict__ A, int64_t lda, int64_t m, int64_t k,
                                       uint64_t* __restrict__ planes, int64_t Mp, int64_t K64p,
                                       int* __restrict__ err, int64_t r, int64_t kw)
@@ -104,12 +106,12 @@ __device__ __attribute__((always_inline)) inline void slice_row_word(const void*
     if (bad) atomicOr(err, 1);
     uint64_t pl[E];
     bytes_to_planes<E>(lo, hi, pl);
-    store_operands<E>(pl, planes + kw * Mp + r, K64p * Mp);
+    store_operands<E, SID, false>(pl, planes + kw * Mp + r, K64p * Mp);
 }
 
 // Column slicing of one plane word: column j of B, k-bits [64kw, 64kw+64).
 // Consecutive threads take consecutive columns, so every load is coalesced.
-template <int E>
+template <int E, int SID>
 __device__ __attribute__((always_inline)) inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
                                       uint64_t* __restrict__ planes, int64_t Np, int64_t K64p,
                                       int* __restrict__ err, int64_t j, int64_t kw)
@@ -134,41 +136,54 @@ __device__ __attribute__((always_inline)) inline void slice_col_word(const void*
     if (bad) atomicOr(err, 1);
     uint64_t pl[E];
     bytes_to_planes<E>(lo, hi, pl);
-    store_operands<E>(pl, planes + kw * Np + j, K64p * Np);
+    store_operands<E, SID, true>(pl, planes + kw * Np + j, K64p * Np);
 }
 
 // Combine of one word: word w of row i of every product plane becomes 64
 // elements of C.  k0 set: the product has an empty inner dimension, C = 0.
-template <int E>
+template <int E, int SID>
 __device__ __attribute__((always_inline)) inline void combine_word(const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp,
                                     int64_t n, uint32_t f, void* __restrict__ C, int64_t ldc,
                                     int64_t i, int64_t w, bool k0)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
-    constexpr Schedule S = build_schedule(E);
+    constexpr KernelSchedule S = kernel_schedule(E, SID);
     constexpr int D = 2 * E - 1;
     uint64_t p[S.t];
 #pragma unroll
     for (int s = 0; s < S.t; ++s) p[s] = k0 ? 0ull : P[s * Mp * ldp + i * ldp + w];
 
-    // Coefficient planes of the polynomial product: C~_d = XOR_{s in w[d]} P_s.
     uint64_t c[D];
+    if constexpr (S.folded) {
+        // The schedule already reduces modulo its f: plane q is the XOR of
+        // the products whose output set holds q.
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        uint64_t x = 0;
+        for (int q = 0; q < E; ++q) {
+            uint64_t x = 0;
 #pragma unroll
-        for (int s = 0; s < S.t; ++s)
-            if ((S.w[d] >> s) & 1u) x ^= p[s];
-        c[d] = x;
+            for (int s = 0; s < S.t; ++s)
+                if ((S.c[s] >> q) & 1u) x ^= p[s];
+            c[q] = x;
+        }
+    } else {
+        // Coefficient planes of the polynomial product: C~_d = XOR_{s in w[d]} P_s.
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            uint64_t x = 0;
+#pragma unroll
+            for (int s = 0; s < S.t; ++s)
+                if ((S.w[d] >> s) & 1u) x ^= p[s];
+            c[d] = x;
+        }
+        // Reduction modulo f: x^d = x^(d-E) * (f - x^E) for d >= E, highest first.
+        uint64_t fm[E];
+#pragma unroll
+        for (int b = 0; b < E; ++b) fm[b] = 0ull - uint64_t((f >> b) & 1u);
+#pragma unroll
+        for (int d = D - 1; d >= E; --d)
+#pragma unroll
+            for (int b = 0; b < E; ++b) c[d - E + b] ^= c[d] & fm[b];
     }
-    // Reduction modulo f: x^d = x^(d-E) * (f - x^E) for d >= E, highest first.
-    uint64_t fm[E];
-#pragma unroll
-    for (int b = 0; b < E; ++b) fm[b] = 0ull - uint64_t((f >> b) & 1u);
-#pragma unroll
-    for (int d = D - 1; d >= E; --d)
-#pragma unroll
-        for (int b = 0; b < E; ++b) c[d - E + b] ^= c[d] & fm[b];
 
     // Cling: element 64w + 8g + b takes bit (8g + b) of planes 0..E-1.
     elem_t out[64];
@@ -212,27 +227,27 @@ __device__ __attribute__((always_inline)) inline void combine_word(const uint64_
         if (b < valid) dst[b] = out[b];
 }
 
-template <int E>
+template <int E, int SID>
 __global__ __launch_bounds__(kThreads) void slice_rows_kernel(
     const void* __restrict__ A, int64_t lda, int64_t m, int64_t k, uint64_t* __restrict__ planes,
     int64_t Mp, int64_t K64p, int* __restrict__ err)
 {
     const int64_t r = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (r >= Mp) return;
-    slice_row_word<E>(A, lda, m, k, planes, Mp, K64p, err, r, blockIdx.y);
+    slice_row_word<E, SID>(A, lda, m, k, planes, Mp, K64p, err, r, blockIdx.y);
 }
 
-template <int E>
+template <int E, int SID>
 __global__ __launch_bounds__(kThreads) void slice_cols_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
     const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (j >= Np) return;
-    slice_col_word<E>(B, ldb, k, n, planes, Np, K64p, err, j, blockIdx.y);
+    slice_col_word<E, SID>(B, ldb, k, n, planes, Np, K64p, err, j, blockIdx.y);
 }
 
-template <int E>
+template <int E, int SID>
 __global__ __launch_bounds__(kThreads) void combine_kernel(
     const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp, int64_t m, int64_t n, uint32_t f,
     void* __restrict__ C, int64_t ldc)
@@ -241,26 +256,46 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(
     const int64_t w = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (w >= nw) return;
     for (int64_t i = blockIdx.y; i < m; i += gridDim.y)
-        combine_word<E>(P, Mp, ldp, n, f, C, ldc, i, w, false);
+        combine_word<E, SID>(P, Mp, ldp, n, f, C, ldc, i, w, false);
 }
 
 // ---------------------------------------------------------------------------
 // Batched forms: blockIdx.y selects the product, blockIdx.x a 256-thread job
 // of that product (blocks past the product's job count return at once).
 // ---------------------------------------------------------------------------
-#define GF2E_SWITCH_E(e, CALL) \
-    switch (e) {               \
-        case 2: CALL(2); break;  \
-        case 3: CALL(3); break;  \
-        case 4: CALL(4); break;  \
-        case 5: CALL(5); break;  \
-        case 6: CALL(6); break;  \
-        case 7: CALL(7); break;  \
-        case 8: CALL(8); break;  \
-        case 9: CALL(9); break;  \
-        case 10: CALL(10); break; \
-        default: break;          \
+// Calls fn.template operator()<E, SID>() for the schedule of (e, sid): the
+// Karatsuba schedules (sid < 0) for e = 2..10, or field schedule sid.
+template <int I, class Fn>
+__host__ __device__ inline bool with_field_schedule(int sid, Fn& fn)
+{
+    if constexpr (I < kNumFieldSchedules) {
+        if (sid == I) {
+            fn.template operator()<kFieldSchedules[I].e, I>();
+            return true;
+        }
+        return with_field_schedule<I + 1>(sid, fn);
+    } else {
+        return false;
     }
+}
+
+template <class Fn>
+__host__ __device__ inline bool with_schedule(int e, int sid, Fn&& fn)
+{
+    if (sid >= 0) return with_field_schedule<0>(sid, fn);
+    switch (e) {
+        case 2: fn.template operator()<2, -1>(); return true;
+        case 3: fn.template operator()<3, -1>(); return true;
+        case 4: fn.template operator()<4, -1>(); return true;
+        case 5: fn.template operator()<5, -1>(); return true;
+        case 6: fn.template operator()<6, -1>(); return true;
+        case 7: fn.template operator()<7, -1>(); return true;
+        case 8: fn.template operator()<8, -1>(); return true;
+        case 9: fn.template operator()<9, -1>(); return true;
+        case 10: fn.template operator()<10, -1>(); return true;
+        default: return false;
+    }
+}
 
 __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProduct* __restrict__ prods,
                                                                  int* __restrict__ err)
@@ -270,18 +305,18 @@ __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProd
     if (job < P.slice_a_blocks) {
         const int64_t rb_count = P.Mp / kThreads;
         const int64_t r = (job % rb_count) * kThreads + threadIdx.x, kw = job / rb_count;
-#define S_(E) slice_row_word<E>(P.A, P.lda, P.m, P.k, P.Apl, P.Mp, P.K64p, err, r, kw)
-        GF2E_SWITCH_E(P.e, S_)
-#undef S_
+        with_schedule(P.e, P.sid, [&]<int E, int SID>() {
+            slice_row_word<E, SID>(P.A, P.lda, P.m, P.k, P.Apl, P.Mp, P.K64p, err, r, kw);
+        });
         return;
     }
     job -= P.slice_a_blocks;
     if (job < P.slice_b_blocks) {
         const int64_t cb_count = P.Np / kThreads;
         const int64_t j = (job % cb_count) * kThreads + threadIdx.x, kw = job / cb_count;
-#define S_(E) slice_col_word<E>(P.B, P.ldb, P.k, P.n, P.Bpl, P.Np, P.K64p, err, j, kw)
-        GF2E_SWITCH_E(P.e, S_)
-#undef S_
+        with_schedule(P.e, P.sid, [&]<int E, int SID>() {
+            slice_col_word<E, SID>(P.B, P.ldb, P.k, P.n, P.Bpl, P.Np, P.K64p, err, j, kw);
+        });
     }
 }
 
@@ -293,9 +328,9 @@ __global__ __launch_bounds__(kThreads) void batched_combine_kernel(const BatchPr
     const int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (idx >= P.m * nw) return;
     const int64_t i = idx / nw, w = idx % nw;
-#define C_(E) combine_word<E>(P.P, P.Mp, P.Np / 64, P.n, P.f, P.C, P.ldc, i, w, P.k == 0)
-    GF2E_SWITCH_E(P.e, C_)
-#undef C_
+    with_schedule(P.e, P.sid, [&]<int E, int SID>() {
+        combine_word<E, SID>(P.P, P.Mp, P.Np / 64, P.n, P.f, P.C, P.ldc, i, w, P.k == 0);
+    });
 }
 
 __global__ void zero_kernel(uint8_t* C, int64_t rows, int64_t row_bytes, int64_t ld_bytes)
@@ -308,53 +343,42 @@ __global__ void zero_kernel(uint8_t* C, int64_t rows, int64_t row_bytes, int64_t
 
 }  // namespace
 
-#define GF2E_DISPATCH_E(e, CALL)         \
-    switch (e) {                         \
-        case 2: CALL(2); break;          \
-        case 3: CALL(3); break;          \
-        case 4: CALL(4); break;          \
-        case 5: CALL(5); break;          \
-        case 6: CALL(6); break;          \
-        case 7: CALL(7); break;          \
-        case 8: CALL(8); break;          \
-        case 9: CALL(9); break;          \
-        case 10: CALL(10); break;        \
-        default: return hipErrorInvalidValue; \
-    }
-
-hipError_t launch_slice_rows(int e, const void* A, int64_t lda, int64_t m, int64_t k,
+hipError_t launch_slice_rows(int e, int sid, const void* A, int64_t lda, int64_t m, int64_t k,
                              uint64_t* planes, int64_t Mp, int64_t K64p, int* err, hipStream_t s)
 {
     if (Mp <= 0 || K64p <= 0) return hipSuccess;
     dim3 grid(unsigned(ceil_div(Mp, kThreads)), unsigned(K64p));
-#define L_(E) hipLaunchKernelGGL(slice_rows_kernel<E>, grid, dim3(kThreads), 0, s, A, lda, m, k, \
-                                 planes, Mp, K64p, err)
-    GF2E_DISPATCH_E(e, L_)
-#undef L_
+    if (!with_schedule(e, sid, [&]<int E, int SID>() {
+            hipLaunchKernelGGL((slice_rows_kernel<E, SID>), grid, dim3(kThreads), 0, s, A, lda, m, k, planes,
+                               Mp, K64p, err);
+        }))
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_slice_cols(int e, const void* B, int64_t ldb, int64_t k, int64_t n,
+hipError_t launch_slice_cols(int e, int sid, const void* B, int64_t ldb, int64_t k, int64_t n,
                              uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s)
 {
     if (Np <= 0 || K64p <= 0) return hipSuccess;
     dim3 grid(unsigned(ceil_div(Np, kThreads)), unsigned(K64p));
-#define L_(E) hipLaunchKernelGGL(slice_cols_kernel<E>, grid, dim3(kThreads), 0, s, B, ldb, k, n, \
-                                 planes, Np, K64p, err)
-    GF2E_DISPATCH_E(e, L_)
-#undef L_
+    if (!with_schedule(e, sid, [&]<int E, int SID>() {
+            hipLaunchKernelGGL((slice_cols_kernel<E, SID>), grid, dim3(kThreads), 0, s, B, ldb, k, n, planes,
+                               Np, K64p, err);
+        }))
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int e, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp, int64_t m,
-                          int64_t n, void* C, int64_t ldc, hipStream_t s)
+hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
+                          int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
     dim3 grid(unsigned(ceil_div(ceil_div(n, 64), kThreads)), unsigned(m < 65535 ? m : 65535));
-#define L_(E) hipLaunchKernelGGL(combine_kernel<E>, grid, dim3(kThreads), 0, s, P, Mp, ldp, m, n, \
-                                 f, C, ldc)
-    GF2E_DISPATCH_E(e, L_)
-#undef L_
+    if (!with_schedule(e, sid, [&]<int E, int SID>() {
+            hipLaunchKernelGGL((combine_kernel<E, SID>), grid, dim3(kThreads), 0, s, P, Mp, ldp, m, n, f, C,
+                               ldc);
+        }))
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -202,9 +202,9 @@ bool Server::admit()
                              hipMemcpyHostToDevice, stream);
         int* err = d_err + r->slot;
         if (r->d.k > 0) {
-            (void)launch_slice_rows(r->d.e, r->d.A, r->d.lda, r->d.m, r->d.k, r->d.Apl, r->d.Mp,
+            (void)launch_slice_rows(r->d.e, r->d.sid, r->d.A, r->d.lda, r->d.m, r->d.k, r->d.Apl, r->d.Mp,
                                     r->d.K64p, err, stream);
-            (void)launch_slice_cols(r->d.e, r->d.B, r->d.ldb, r->d.k, r->d.n, r->d.Bpl, r->d.Np,
+            (void)launch_slice_cols(r->d.e, r->d.sid, r->d.B, r->d.ldb, r->d.k, r->d.n, r->d.Bpl, r->d.Np,
                                     r->d.K64p, err, stream);
         }
         r->t_admit = now_ns();
@@ -265,7 +265,7 @@ bool Server::issue_iteration()
         if (r->d.k == 0)
             (void)launch_zero(r->d.C, r->d.m, r->d.n, r->d.ldc, elem_bytes(r->d.e), stream);
         else
-            (void)launch_combine(r->d.e, r->d.f, r->d.P, r->d.Mp, r->d.Np / 64, r->d.m, r->d.n, r->d.C,
+            (void)launch_combine(r->d.e, r->d.sid, r->d.f, r->d.P, r->d.Mp, r->d.Np / 64, r->d.m, r->d.n, r->d.C,
                                  r->d.ldc, stream);
         (void)hipMemcpyAsync(h_err + r->slot, d_err + r->slot, sizeof(int), hipMemcpyDeviceToHost, stream);
         (void)launch_reset_counters(d_err + r->slot, 1, stream);
@@ -397,7 +397,7 @@ int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B
     if (rc) return rc;
     const int64_t m = A->rows, k = A->cols, n = B->cols;
     auto r = std::make_unique<Request>();
-    r->plan = make_plan(e, std::max<int64_t>(m, 1), std::max<int64_t>(k, 1), std::max<int64_t>(n, 1));
+    r->plan = make_plan(e, f, std::max<int64_t>(m, 1), std::max<int64_t>(k, 1), std::max<int64_t>(n, 1));
     r->footprint = footprint_of(r->plan);
     if (r->footprint > s->cfg.memory_budget) return GF2E_EBUSY;  // can never be admitted
     BatchProduct& d = r->d;
@@ -405,7 +405,7 @@ int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B
     d.lda = A->ld; d.ldb = B->ld; d.ldc = C->ld;
     d.m = m; d.k = k; d.n = n;
     d.Mp = r->plan.Mp; d.Np = r->plan.Np; d.K64p = r->plan.K64p;
-    d.e = e; d.T = r->plan.T; d.f = f;
+    d.e = e; d.T = r->plan.T; d.f = f; d.sid = r->plan.sid;
     r->cls = (std::min(m, n) >= s->ctx->batch_threshold ? 0 : 1) +
              (r->plan.K64p * 64 <= (int64_t(1) << 24) ? 0 : 2);
     const GemmShape sh = gemm_shape(kClassKinds[r->cls]);

@@ -43,7 +43,7 @@ def host_u64(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-@pytest.mark.parametrize("e", [2, 3, 4, 8, 9, 10])
+@pytest.mark.parametrize("e", [2, 3, 4, 5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_slice_a_and_b(g, ctx, e, shape):
     m, k, n = shape
@@ -52,12 +52,12 @@ def test_slice_a_and_b(g, ctx, e, shape):
     gen = np.random.default_rng(e * 7919 + m)
     A = workload.field_matrix(gen, m, k, e)
     B = workload.field_matrix(gen, k, n, e)
-    geo = g.plane_geometry(e, m, k, n)
+    geo = g.plane_geometry(e, f, m, k, n)
     S = g.schedule(e, f)
     Ap = torch.full((geo.t, geo.K64p, geo.Mp), -1, dtype=torch.int64, device="cuda")
     Bp = torch.full((geo.t, geo.K64p, geo.Np), -1, dtype=torch.int64, device="cuda")
-    ctx.slice_a(dev(A, e), e, Ap, geo.Mp, geo.K64p)
-    ctx.slice_b(dev(B, e), e, Bp, geo.Np, geo.K64p)
+    ctx.slice_a(dev(A, e), e, f, Ap, geo.Mp, geo.K64p)
+    ctx.slice_b(dev(B, e), e, f, Bp, geo.Np, geo.K64p)
     ctx.sync()
     assert (host_u64(Ap) == pm.operand_planes_a(A, e, S["u"], geo.Mp, geo.K64p)).all()
     assert (host_u64(Bp) == pm.operand_planes_b(B, e, S["v"], geo.Np, geo.K64p)).all()
@@ -71,10 +71,10 @@ def test_slice_figure1(g, ctx, golden_dir):
     meta, _ = fielddef.read_golden(os.path.join(golden_dir, "fig1_f8.txt"))
     e = meta["e"][0]
     A = np.array(meta["packed"], dtype=np.uint8).reshape(2, 2)
-    geo = g.plane_geometry(e, 2, 2, 2)
+    geo = g.plane_geometry(e, 0xB, 2, 2, 2)
     S = g.schedule(e, 0xB)
     Ap = torch.zeros((geo.t, geo.K64p, geo.Mp), dtype=torch.int64, device="cuda")
-    ctx.slice_a(dev(A, e), e, Ap, geo.Mp, geo.K64p)
+    ctx.slice_a(dev(A, e), e, 0xB, Ap, geo.Mp, geo.K64p)
     ctx.sync()
     planes = host_u64(Ap)
     for i in range(e):
@@ -90,7 +90,7 @@ def test_plane_products(g, ctx, kind, shape):
     m, k, n = shape
     print(f"products kind={kind} shape={shape}", flush=True)
     t = 5
-    geo = g.plane_geometry(2, m, k, n)
+    geo = g.plane_geometry(2, 0x7, m, k, n)
     gen = np.random.default_rng(kind * 100 + m)
     # Arbitrary words everywhere, padding included: the product runs over all
     # K64p*64 bits, and only rows < m, columns < n are compared.
@@ -113,7 +113,7 @@ def test_plane_products(g, ctx, kind, shape):
 def test_combine(g, ctx, e, f, mn):
     m, n = mn
     print(f"combine e={e} f={f:#x} m={m} n={n}", flush=True)
-    geo = g.plane_geometry(e, m, 1, n)
+    geo = g.plane_geometry(e, f, m, 1, n)
     S = g.schedule(e, f)
     gen = np.random.default_rng(e * 31 + m)
     Ph = rand_words(gen, (geo.t, geo.Mp, geo.Np // 64))
