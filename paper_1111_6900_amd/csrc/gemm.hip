@@ -189,13 +189,16 @@ __global__ void reset_counters_kernel(int* counters, int n)
 }
 
 // ---------------------------------------------------------------------------
-// FP4 MFMA path (v_mfma_scale_f32_16x16x128_f8f6f4, both operands e2m1): every
-// bit becomes a nibble that is 0 or 1.0 (0b0010), scales are 2^0, so each
-// f32 accumulator holds the exact count of common ones (exact below 2^24;
-// launches with more k are refused).  The low bit of that count is the GF(2)
-// product, as in the int8 path, at twice its MFMA rate and half its staging
-// bytes.  A stage holds KB consecutive 128-bit k-blocks; block b of a row is
-// stored as 4 chunks of 32 nibbles, chunk c from 32-bit word c of the block.
+// FP4 MFMA path (v_mfma_f32_16x16x128_f8f6f4, both operands e2m1, no block
+// scales): every bit becomes a nibble that is 0 or a power of two, chosen per
+// side so that each product of two set bits is exactly 1.0.  Each f32
+// accumulator then holds the exact count of common ones (exact below 2^24;
+// launches with more k are refused), and its low bit is the GF(2) product, as
+// in the int8 path, at twice its MFMA rate.  A stage holds KB consecutive
+// 128-bit k-blocks; how each side sits in LDS (packed, split or expanded, see
+// Fp4Side) trades VALU work in the reading waves against LDS bytes.  With
+// operands expanded before the store the kernel was bound by LDS traffic;
+// with all expansion in the reading waves, by VALU issue next to the MFMAs.
 // ---------------------------------------------------------------------------
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -210,27 +213,124 @@ __device__ inline v8i fp4_operand(const uint4& x)
     return __builtin_shufflevector(v, v, 0, 1, 2, 3, -1, -1, -1, -1);
 }
 
-// Chunk of 32-bit word h: nibble j of dword q is 1.0 iff bit 4j+q of h is set.
-__device__ inline uint4 expand_fp4(uint32_t h)
+// Nibble codes.  Dword q of an operand holds k-bits 4j+q (j < 8) of a 32-bit
+// chunk h as nibble j; e2m1 codes 0b0001, 0b0010 and 0b0100 are 0.5, 1.0 and
+// 2.0.  The A side gives dwords q = 0..3 the values 0.5, 1, 2, 2 and the B
+// side 2, 1, 0.5, 0.5, so the product of two set bits is exactly 1.0 for
+// every q and the f32 accumulator counts common ones.  On the A side bit q of
+// a nibble already is the code of its value for q < 3, so its expansion is
+// mostly masks.
+template <bool BSIDE>
+__device__ __attribute__((always_inline)) inline uint4 expand_fp4(uint32_t h)
 {
-    const uint32_t M = 0x22222222u;
-    return make_uint4((h << 1) & M, h & M, (h >> 1) & M, (h >> 2) & M);
+    if constexpr (!BSIDE)
+        return make_uint4(h & 0x11111111u, h & 0x22222222u, h & 0x44444444u, (h >> 1) & 0x44444444u);
+    else
+        return make_uint4((h << 2) & 0x44444444u, h & 0x22222222u, (h >> 2) & 0x11111111u,
+                          (h >> 3) & 0x11111111u);
 }
 
-template <int BM, int BN, int WM, int WN, int KB>
+// Split form of a chunk: dwords 0..2 of the expansion use disjoint bits and
+// share one word, dword 3 is the other; expanding it again takes three masks.
+template <bool BSIDE>
+__device__ __attribute__((always_inline)) inline uint2 split_fp4(uint32_t h)
+{
+    const uint4 d = expand_fp4<BSIDE>(h);
+    return make_uint2(d.x | d.y | d.z, d.w);
+}
+
+template <bool BSIDE>
+__device__ __attribute__((always_inline)) inline uint4 unsplit_fp4(uint2 s)
+{
+    if constexpr (!BSIDE)
+        return make_uint4(s.x & 0x11111111u, s.x & 0x22222222u, s.x & 0x44444444u, s.y);
+    else
+        return make_uint4(s.x & 0x44444444u, s.x & 0x22222222u, s.x & 0x11111111u, s.y);
+}
+
+// Orders a stage's products before the LDS stores that follow them.  Those
+// stores fill the other buffer with data loaded at the top of the stage; the
+// compiler may otherwise sink the products below them, so that each wave
+// waits for its global loads right after issuing them.  The empty asm
+// statements read and write every accumulator (no instruction is emitted),
+// and the last one is a memory barrier.
+template <int FM, int FN>
+__device__ __attribute__((always_inline)) inline void products_before_stores(v4f (&acc)[FM][FN])
+{
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) asm volatile("" : "+v"(acc[i][j]));
+    asm volatile("" ::: "memory");
+}
+
+// One operand side (A rows or B columns) of the double-buffered stage in
+// LDS, in one of three forms.  Packed: one 32-bit chunk per (chunk, row),
+// expanded by every wave that reads it (VALU work per wave).  Expanded: the
+// 16-byte nibble form, built once by the staging thread (four times the LDS
+// bytes).  Split: the two-word form (twice the LDS bytes, three masks per
+// read).
+enum Fp4Form : int { kPacked = 0, kExpanded = 1, kSplit = 2 };
+
+template <int ROWS, int CH, int FORM, bool BSIDE>
+struct Fp4Side;
+
+template <int ROWS, int CH, bool BSIDE>
+struct Fp4Side<ROWS, CH, kPacked, BSIDE> {
+    // Row pitch padded by 16 words: the 4 lane groups of one read (same rows,
+    // chunks 4kb..4kb+3) fall on 4 disjoint sets of 16 banks.
+    uint32_t w[2][CH][ROWS + 16];
+    __device__ __attribute__((always_inline)) void put(int buf, int c, int r, uint32_t h) { w[buf][c][r] = h; }
+    __device__ __attribute__((always_inline)) v8i get(int buf, int c, int r) const
+    {
+        return fp4_operand(expand_fp4<BSIDE>(w[buf][c][r]));
+    }
+};
+
+template <int ROWS, int CH, bool BSIDE>
+struct Fp4Side<ROWS, CH, kExpanded, BSIDE> {
+    uint4 w[2][CH][ROWS];
+    __device__ __attribute__((always_inline)) void put(int buf, int c, int r, uint32_t h)
+    {
+        w[buf][c][r] = expand_fp4<BSIDE>(h);
+    }
+    __device__ __attribute__((always_inline)) v8i get(int buf, int c, int r) const
+    {
+        return fp4_operand(w[buf][c][r]);
+    }
+};
+
+template <int ROWS, int CH, bool BSIDE>
+struct Fp4Side<ROWS, CH, kSplit, BSIDE> {
+    // Pitch padded by 16 rows (128 bytes): the two lane groups of a half-wave
+    // read fall on disjoint halves of the banks.
+    uint2 w[2][CH][ROWS + 16];
+    __device__ __attribute__((always_inline)) void put(int buf, int c, int r, uint32_t h)
+    {
+        w[buf][c][r] = split_fp4<BSIDE>(h);
+    }
+    __device__ __attribute__((always_inline)) v8i get(int buf, int c, int r) const
+    {
+        return fp4_operand(unsplit_fp4<BSIDE>(w[buf][c][r]));
+    }
+};
+
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
 __device__ __attribute__((always_inline)) inline void fp4_tile(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
     int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
 {
     using TL = MfmaTile<BM, BN, WM, WN>;
     constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
-    constexpr int CH = 4 * KB;  // chunks per row per stage
-    __shared__ uint4 lds[2][CH][BM + BN];
+    constexpr int CH = 4 * KB;  // 32-bit chunks per row per stage
+    __shared__ Fp4Side<BM, CH, FA, false> sa;
+    __shared__ Fp4Side<BN, CH, FB, true> sb;
     const uint64_t* Ap = Apl + int64_t(tile_m) * BM;
     const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
     static_assert(KB == 2, "stages are whole 256-bit k-steps (K64p is a multiple of 4)");
+    static_assert(BM % 64 == 0 && NT % 64 == 0, "a wave stages rows of one side only");
     const int nstages = int(K64p / (2 * KB));
 
     v4f acc[FM][FN];
@@ -239,8 +339,8 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    uint64_t stg[RPT][2 * KB];
-    auto gload = [&](int st) {
+    using Stage = uint64_t[RPT][2 * KB];
+    auto gload = [&](int st, Stage& dst) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int r = tid + q * NT;
@@ -249,46 +349,60 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
                 const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
                 const int64_t ld = isA ? Mp : Np;
 #pragma unroll
-                for (int w = 0; w < 2 * KB; ++w) stg[q][w] = src[(int64_t(st) * 2 * KB + w) * ld];
+                for (int w = 0; w < 2 * KB; ++w) dst[q][w] = src[(int64_t(st) * 2 * KB + w) * ld];
             }
         }
     };
-    auto expand_store = [&](int buf) {
+    auto store = [&](int buf, const Stage& src) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int r = tid + q * NT;
             if (r < TL::kRows) {
+                // BM and NT are multiples of 64, so a wave stages A rows or B
+                // columns only; deciding on lane 0 gives a scalar branch.
+                if (__builtin_amdgcn_readfirstlane(r) < BM) {
 #pragma unroll
-                for (int c = 0; c < CH; ++c)
-                    lds[buf][c][r] = expand_fp4(uint32_t(stg[q][c >> 1] >> (32 * (c & 1))));
+                    for (int c = 0; c < CH; ++c) sa.put(buf, c, r, uint32_t(src[q][c >> 1] >> (32 * (c & 1))));
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        sb.put(buf, c, r - BM, uint32_t(src[q][c >> 1] >> (32 * (c & 1))));
+                }
             }
         }
     };
-
-    gload(0);
-    expand_store(0);
-    __syncthreads();
     const int g = lane >> 4, l16 = lane & 15;
-    for (int st = 0; st < nstages; ++st) {
-        const int buf = st & 1;
-        const bool more = st + 1 < nstages;
-        if (more) gload(st + 1);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const int c = 4 * kb + g;
             v8i a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = fp4_operand(lds[buf][c][wr * WM + 16 * i + l16]);
+            for (int i = 0; i < FM; ++i) a[i] = sa.get(buf, c, wr * WM + 16 * i + l16);
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = fp4_operand(lds[buf][c][BM + wc * WN + 16 * j + l16]);
+            for (int j = 0; j < FN; ++j) b[j] = sb.get(buf, c, wc * WN + 16 * j + l16);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
+                    // Formats 4/4 select e2m1 for both operands; zero scale
+                    // operands make the compiler emit the unscaled form.
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0,
-                                                                                127, 0, 127);
+                                                                                0, 0, 0);
         }
-        if (more) expand_store(buf ^ 1);
+    };
+
+    // Loads for stage st + 1 are in flight while stage st computes.
+    Stage s0;
+    gload(0, s0);
+    store(0, s0);
+    __syncthreads();
+    for (int st = 0; st < nstages; ++st) {
+        const bool more = st + 1 < nstages;
+        if (more) gload(st + 1, s0);
+        compute(st & 1);
+        products_before_stores(acc);
+        if (more) store((st & 1) ^ 1, s0);
         __syncthreads();
     }
 
@@ -313,18 +427,18 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
     }
 }
 
-template <int BM, int BN, int WM, int WN, int KB>
-__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_fp4_kernel(
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_kernel(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
     int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
 {
     const int64_t s = blockIdx.z;
-    fp4_tile<BM, BN, WM, WN, KB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
+    fp4_tile<BM, BN, WM, WN, KB, FA, FB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
                                  Np, K64p, blockIdx.y, blockIdx.x);
 }
 
-template <int BM, int BN, int WM, int WN, int KB>
-__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_fp4_persistent(
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_persistent(
     const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
     int* __restrict__ counter)
 {
@@ -338,7 +452,7 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_fp4
         const WorkItem w = items[it];
         const BatchProduct& P = prods[w.prod];
         const int64_t s = w.plane;
-        fp4_tile<BM, BN, WM, WN, KB>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
+        fp4_tile<BM, BN, WM, WN, KB, FA, FB>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
                                      P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
                                      w.tile_n);
     }
@@ -450,7 +564,7 @@ hipError_t launch_mfma(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t
     return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN, int KB>
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
 hipError_t launch_fp4(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P, int64_t m,
                       int64_t n, int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
 {
@@ -458,7 +572,7 @@ hipError_t launch_fp4(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t*
     const int tm = int(ceil_div(m, BM)), tn = int(ceil_div(n, BN));
     if (tm * int64_t(BM) > Mp || tn * int64_t(BN) > Np || K64p * 64 > kFp4MaxK) return hipErrorInvalidValue;
     dim3 grid(tn, tm, T);
-    hipLaunchKernelGGL((gemm_fp4_kernel<BM, BN, WM, WN, KB>), grid, dim3(TL::kThreads), 0, st, Apl, Bpl,
+    hipLaunchKernelGGL((gemm_fp4_kernel<BM, BN, WM, WN, KB, FA, FB>), grid, dim3(TL::kThreads), 0, st, Apl, Bpl,
                        P, Mp, Np, K64p, tm, tn);
     return hipGetLastError();
 }
@@ -493,10 +607,10 @@ int persistent_grid(int kind)
         case GEMM_MFMA_256x256_W8: return persistent_blocks<256, 256, 128, 64>();
         case GEMM_MFMA_128x128: return persistent_blocks<128, 128, 64, 64>();
         case GEMM_FP4_256x256_W8:
-            return blocks_filling_device(gemm_fp4_persistent<256, 256, 128, 64, 2>,
+            return blocks_filling_device(gemm_fp4_persistent<256, 256, 128, 64, 2, kSplit, kPacked>,
                                          MfmaTile<256, 256, 128, 64>::kThreads);
         case GEMM_FP4_128x128:
-            return blocks_filling_device(gemm_fp4_persistent<128, 128, 64, 64, 2>,
+            return blocks_filling_device(gemm_fp4_persistent<128, 128, 64, 64, 2, kPacked, kPacked>,
                                          MfmaTile<128, 128, 64, 64>::kThreads);
         default: return 0;
     }
@@ -519,12 +633,12 @@ hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const Wor
                                counter);
             break;
         case GEMM_FP4_256x256_W8:
-            hipLaunchKernelGGL((gemm_fp4_persistent<256, 256, 128, 64, 2>), dim3(grid),
+            hipLaunchKernelGGL((gemm_fp4_persistent<256, 256, 128, 64, 2, kSplit, kPacked>), dim3(grid),
                                dim3(MfmaTile<256, 256, 128, 64>::kThreads), 0, s, prods, items, nitems,
                                counter);
             break;
         case GEMM_FP4_128x128:
-            hipLaunchKernelGGL((gemm_fp4_persistent<128, 128, 64, 64, 2>), dim3(grid),
+            hipLaunchKernelGGL((gemm_fp4_persistent<128, 128, 64, 64, 2, kPacked, kPacked>), dim3(grid),
                                dim3(MfmaTile<128, 128, 64, 64>::kThreads), 0, s, prods, items, nitems,
                                counter);
             break;
@@ -589,9 +703,9 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
         case GEMM_MFMA_256x256_W8:
             return launch_mfma<256, 256, 128, 64>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_FP4_256x256_W8:
-            return launch_fp4<256, 256, 128, 64, 2>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+            return launch_fp4<256, 256, 128, 64, 2, kSplit, kPacked>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
         case GEMM_FP4_128x128:
-            return launch_fp4<128, 128, 64, 64, 2>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+            return launch_fp4<128, 128, 64, 64, 2, kPacked, kPacked>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
 
         case GEMM_VALU_128x128: {
             const int tm = int(ceil_div(m, kValuTile)), tn = int(ceil_div(n, kValuTile));
