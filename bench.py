@@ -66,6 +66,7 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
@@ -145,6 +146,39 @@ def batched_leg(g, torch, workload, log, reps=5):
             "work_items": info["items_large"] + info["items_small"],
             "tile_threshold": info["threshold"],
             "plane_arena_bytes": info["arena_bytes"]}
+
+
+def forms_leg(g, torch, workload, log, reps=10):
+    """Both forms of the plain product (schedule products vs one alpha-power
+    product) on the three plain workloads, each with its tuned kernel."""
+    res = {}
+    for name, (e, f, m, k, n) in workload.PLAIN_CONFIGS.items():
+        _, _, A, B = workload.plain_inputs(name)
+        Ad = torch.from_numpy(A).to(g.elem_dtype(e)).cuda()
+        Bd = torch.from_numpy(B).to(g.elem_dtype(e)).cuda()
+        C = torch.empty((m, n), dtype=g.elem_dtype(e), device="cuda")
+        ctx = g.Context(0, autotune=True)
+        ctx.tune(e, f, m, k, n)
+        row = {"e": e, "m": m, "k": k, "n": n,
+               "chosen": ["schedule", "alpha"][ctx.chosen_form(e, f, m, k, n)]}
+        for form, label in [(g.FORM_SCHEDULE, "schedule"), (g.FORM_ALPHA, "alpha")]:
+            ctx.set_form(form)
+            for _ in range(2):
+                ctx.mul_async(Ad, Bd, e, f, out=C)
+            ctx.sync()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ctx.mul_async(Ad, Bd, e, f, out=C)
+            e1.record()
+            ctx.sync()
+            row[f"{label}_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+            row[f"{label}_kernel"] = g.kernel_names()[ctx.chosen_kernel(e, f, m, k, n)]
+        log(f"forms {name}: {row}")
+        res[name] = row
+        ctx.close()
+        del Ad, Bd, C
+    return res
 
 
 def serve_leg(g, torch, workload, log, count=10000, budget=4 << 30, max_inflight=64, load=0.7):
@@ -237,7 +271,7 @@ def main():
     C = torch.empty((m, n), dtype=g.elem_dtype(e), device="cuda")
 
     if args.profile_run:
-        args.no_cpu = args.no_batched = args.no_serve = True
+        args.no_cpu = args.no_batched = args.no_serve = args.no_forms = True
         # A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
         # counters calibrate the byte counts read for the product kernels.
         src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -252,7 +286,8 @@ def main():
         ctx.mul_async(Ad, Bd, e, f, out=C)
     ctx.sync()
     kind = ctx.chosen_kernel(e, f, m, k, n)
-    log(args, f"product kernel: {g.kernel_names()[kind]}")
+    form = ctx.chosen_form(e, f, m, k, n)
+    log(args, f"form {form}, product kernel: {g.kernel_names()[kind]}")
 
     ctx.profile(True)
     ctx.profile_reset()
@@ -272,21 +307,29 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = m * k * n / (ms_per_step / 1e3)
 
-    T = g.num_products(e, f)
+    # GF(2) products of m x k x n per element product: t(e) for the schedule
+    # form, e^2 (as one product of m x ek x en) for the alpha form.
+    T = g.num_products(e, f) if form == g.FORM_SCHEDULE else e * e
     prod_ms = stages["products"]
     kname = g.kernel_names()[kind]
     bound, peak, unit, ops_per_mac = kernel_roofline(kname)
-    ops = ops_per_mac * T * m * n * k  # algorithmic: t(e) GF(2) products of m x k x n
+    ops = ops_per_mac * T * m * n * k  # algorithmic: T GF(2) products of m x k x n
+    # Operand planes read once and product planes written once.
+    kwa, nwa = -(-k // 64), -(-n // 64)
+    if form == g.FORM_SCHEDULE:
+        plane_bytes = 8 * T * (kwa * (m + n) + m * nwa)
+    else:
+        plane_bytes = 8 * (e * kwa * m + e * e * kwa * n + e * m * nwa)
     achieved = ops / (prod_ms / 1e3) / 1e12
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(args.workload, kname),
-                "kernel": kname, "avg_launch_ms": round(prod_ms, 4),
+                "kernel": kname, "form": ["schedule", "alpha"][form], "avg_launch_ms": round(prod_ms, 4),
                 "algorithmic_ops_per_launch": ops,
-                "algorithmic_bytes_per_launch": 8 * T * ((-(-k // 64)) * (m + n) + m * (-(-n // 64)))}
+                "algorithmic_bytes_per_launch": plane_bytes}
     # HBM-bound stages: algorithmic bytes (elements in/out + planes written/read).
     esz = 1 if e <= 8 else 2
-    kw = 2 * -(-k // 128)
+    kw = -(-k // 64)
     stage_bytes = {
         "slice_a": m * k * esz + T * kw * m * 8,
         "slice_b": k * n * esz + T * kw * n * 8,
@@ -329,6 +372,8 @@ def main():
         out["valu_products_ms"] = round(ms / max(cnt, 1), 4)
         vctx.close()
 
+    if not args.no_forms:
+        out["forms"] = forms_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_batched:
         out["batched"] = batched_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_serve:

@@ -243,10 +243,32 @@ int gf2e_combine(gf2e_ctx* ctx, int e, uint32_t f, const uint64_t* p_planes, int
 int gf2e_kernel_count(void);
 const char* gf2e_kernel_name(int kernel);
 int gf2e_set_kernel(gf2e_ctx* ctx, int kernel);
-/* Kernel the planner would use now for an (e, f, m, k, n) product. */
+/* Kernel the planner would use now for an (e, f, m, k, n) product (for the
+ * form it would use). */
 int gf2e_chosen_kernel(gf2e_ctx* ctx, int e, uint32_t f, int64_t m, int64_t k, int64_t n);
-/* Time every candidate kernel for this shape now and cache the fastest. */
+/* Time every candidate kernel for this shape, for both forms, then both
+ * whole pipelines, and cache the fastest form and kernel.  Runs on inputs
+ * of zeros in the context's workspace; the caller's data is not touched. */
 int gf2e_tune(gf2e_ctx* ctx, int e, uint32_t f, int64_t m, int64_t k, int64_t n, void* stream);
+
+/* How gf2e_mul computes a product (gf2e_set_form).
+ *  SCHEDULE: slice A and B into the t(e) operand planes of the bilinear
+ *    schedule, t(e) GF(2) products, recombine and reduce modulo f (Section 5).
+ *  ALPHA: write the product as C_c = sum_i A_i * (plane c of x^i B) over the
+ *    bit-planes A_i of A, with x^i B computed in F_2[x]/<f>; that is one GF(2)
+ *    product of the m x ek matrix [A_0 .. A_{e-1}] with the ek x en matrix of
+ *    the planes of x^i B, whose column blocks are the e result planes.  The
+ *    reduction modulo f is folded into the B side: the rows x^k B, k < e, are
+ *    the first table that Section 4 builds for its Newton-John tables
+ *    (Algorithm MakeTable), here on bit-planes.  It costs e^2 bit products per
+ *    element product instead of t(e), in one launch with no recombination;
+ *    the autotuner keeps it for sizes where that is faster.
+ *  AUTO: the tuned form for the size bucket (SCHEDULE until tuned).
+ * Results are identical for every form. */
+enum { GF2E_FORM_AUTO = -1, GF2E_FORM_SCHEDULE = 0, GF2E_FORM_ALPHA = 1 };
+int gf2e_set_form(gf2e_ctx* ctx, int form);
+/* Form the planner would use now for an (e, f, m, k, n) product. */
+int gf2e_chosen_form(gf2e_ctx* ctx, int e, uint32_t f, int64_t m, int64_t k, int64_t n);
 
 /* Stage timers: when enabled, every launch of a stage is bracketed by HIP
  * events on the stream it runs on.  Stages: 0 slice A, 1 slice B,

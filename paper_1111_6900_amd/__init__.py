@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgf2e.so")
 OK, EINVAL, EFIELD, ESHAPE, EALIAS, ERANGE, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
 KERNEL_AUTO, KERNEL_MFMA_256, KERNEL_MFMA_128, KERNEL_MFMA_256x128, KERNEL_MFMA_64, KERNEL_VALU_128, \
     KERNEL_MFMA_256_W8, KERNEL_FP4_256_W8, KERNEL_FP4_128 = -1, 0, 1, 2, 3, 4, 5, 6, 7
+FORM_AUTO, FORM_SCHEDULE, FORM_ALPHA = -1, 0, 1
 STAGE_SLICE_A, STAGE_SLICE_B, STAGE_PRODUCTS, STAGE_COMBINE, STAGE_BATCH = 0, 1, 2, 3, 4
 
 
@@ -105,6 +106,8 @@ _SIGS = {
     "gf2e_set_kernel": (_i32, [_vp, _i32]),
     "gf2e_chosen_kernel": (_i32, [_vp, _i32, _u32, _i64, _i64, _i64]),
     "gf2e_tune": (_i32, [_vp, _i32, _u32, _i64, _i64, _i64, _vp]),
+    "gf2e_set_form": (_i32, [_vp, _i32]),
+    "gf2e_chosen_form": (_i32, [_vp, _i32, _u32, _i64, _i64, _i64]),
     "gf2e_profile": (_i32, [_vp, _i32]),
     "gf2e_profile_read": (_i32, [_vp, _i32, _P(ctypes.c_double), _P(_i64)]),
     "gf2e_profile_reset": (_i32, [_vp]),
@@ -339,6 +342,16 @@ class Context:
 
     def tune(self, e, f, m, k, n, stream=None):
         _check(lib().gf2e_tune(self.handle, e, f, m, k, n, _stream_handle(stream)), "gf2e_tune")
+
+    def set_form(self, form: int):
+        """FORM_AUTO, FORM_SCHEDULE or FORM_ALPHA (see gf2e_set_form)."""
+        _check(lib().gf2e_set_form(self.handle, form), "gf2e_set_form")
+
+    def chosen_form(self, e, f, m, k, n) -> int:
+        rc = lib().gf2e_chosen_form(self.handle, e, f, m, k, n)
+        if rc < 0:
+            raise GF2EError(rc, "gf2e_chosen_form")
+        return rc
 
     def profile(self, enable: bool = True):
         _check(lib().gf2e_profile(self.handle, 1 if enable else 0), "gf2e_profile")

@@ -80,20 +80,37 @@ int schedule_id(int e, uint32_t f)
     return karatsuba_only ? -1 : find_field_schedule(e, f);
 }
 
-Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n)
+Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form)
 {
     Plan p{};
     p.e = e;
     p.f = f;
-    p.sid = schedule_id(e, f);
-    p.T = p.sid >= 0 ? kFieldSchedules[p.sid].t : best_count(e);
+    p.form = form;
     p.m = m; p.k = k; p.n = n;
     p.Mp = round_up(std::max<int64_t>(m, 1), kRowAlign);
     p.Np = round_up(std::max<int64_t>(n, 1), kRowAlign);
     p.K64p = kwords_padded(std::max<int64_t>(k, 1));
-    p.a_bytes = int64_t(p.T) * p.K64p * p.Mp * 8;
-    p.b_bytes = int64_t(p.T) * p.K64p * p.Np * 8;
-    p.p_bytes = int64_t(p.T) * p.Mp * (p.Np / 64) * 8;
+    if (form == kFormAlpha) {
+        p.sid = kIdentitySchedule;
+        p.T = e;
+        p.gT = 1;
+        p.gNp = int64_t(e) * p.Np;
+        p.gn = int64_t(e - 1) * p.Np + std::max<int64_t>(n, 1);
+        p.gK64p = int64_t(e) * p.K64p;
+        p.a_bytes = int64_t(e) * p.K64p * p.Mp * 8;
+        p.b_bytes = p.gK64p * p.gNp * 8;
+        p.p_bytes = p.Mp * (p.gNp / 64) * 8;
+    } else {
+        p.sid = schedule_id(e, f);
+        p.T = p.sid >= 0 ? kFieldSchedules[p.sid].t : best_count(e);
+        p.gT = p.T;
+        p.gn = std::max<int64_t>(n, 1);
+        p.gNp = p.Np;
+        p.gK64p = p.K64p;
+        p.a_bytes = int64_t(p.T) * p.K64p * p.Mp * 8;
+        p.b_bytes = int64_t(p.T) * p.K64p * p.Np * 8;
+        p.p_bytes = int64_t(p.T) * p.Mp * (p.Np / 64) * 8;
+    }
     return p;
 }
 
@@ -179,6 +196,17 @@ static uint64_t bucket_key(int T, int64_t m, int64_t k, int64_t n)
     return (uint64_t(T) << 48) | (lg(m) << 32) | (lg(n) << 16) | lg(k);
 }
 
+// A size bucket is keyed by the schedule form's product count (which depends
+// on e and f) and the rounded log sizes.  Its tuned choice packs the best
+// kernel of each form and the faster form.
+static uint64_t bucket_of(int e, uint32_t f, int64_t m, int64_t k, int64_t n)
+{
+    return bucket_key(make_plan(e, f, m, k, n).T, m, k, n);
+}
+static int pack_choice(int kind0, int kind1, int form) { return (kind0 & 0xFF) | ((kind1 & 0xFF) << 8) | (form << 16); }
+static int choice_kind(int choice, int form) { return (choice >> (8 * form)) & 0xFF; }
+static int choice_form(int choice) { return (choice >> 16) & 0xFF; }
+
 int default_kind(int T, int64_t m, int64_t n)
 {
     const int64_t t256 = int64_t(T) * ceil_div(m, 256) * ceil_div(n, 256);
@@ -191,15 +219,26 @@ int default_kind(int T, int64_t m, int64_t n)
 bool kind_supports(int kind, const Plan& p)
 {
     const bool fp4 = kind == GEMM_FP4_256x256_W8 || kind == GEMM_FP4_128x128;
-    return !fp4 || p.K64p * 64 <= (int64_t(1) << 24);
+    return !fp4 || p.gK64p * 64 <= (int64_t(1) << 24);
+}
+
+int Ctx::choose_form(int e, uint32_t f, int64_t m, int64_t k, int64_t n)
+{
+    if (forced_form >= 0) return forced_form;
+    auto it = tune.find(bucket_of(e, f, m, k, n));
+    if (it != tune.end()) return choice_form(it->second);
+    return kFormSchedule;
 }
 
 int Ctx::choose_kind(const Plan& p)
 {
     if (forced_kind >= 0) return forced_kind;
-    auto it = tune.find(bucket_key(p.T, p.m, p.k, p.n));
-    if (it != tune.end()) return it->second;
-    return default_kind(p.T, p.m, p.n);
+    auto it = tune.find(bucket_of(p.e, p.f, p.m, p.k, p.n));
+    if (it != tune.end()) {
+        const int kind = choice_kind(it->second, p.form);
+        if (kind < GEMM_NUM_KINDS) return kind;
+    }
+    return default_kind(p.gT, p.m, p.gn);
 }
 
 void Ctx::load_tune_cache()
@@ -211,107 +250,173 @@ void Ctx::load_tune_cache()
     char line[256];
     while (std::fgets(line, sizeof line, fp)) {
         unsigned long long key = 0;
-        int kind = -1;
-        if (std::sscanf(line, "{\"arch\": \"gfx950\", \"key\": %llu, \"kernel\": %d", &key, &kind) == 2 &&
-            kind >= 0 && kind < GEMM_NUM_KINDS)
-            tune[key] = kind;
+        int choice = -1;
+        if (std::sscanf(line, "{\"arch\": \"gfx950\", \"key\": %llu, \"choice\": %d", &key, &choice) == 2 &&
+            choice >= 0 && choice_form(choice) < kNumForms)
+            tune[key] = choice;
     }
     std::fclose(fp);
 }
 
-void Ctx::save_tune_entry(uint64_t key, int kind)
+void Ctx::save_tune_entry(uint64_t key, int choice)
 {
     const char* path = std::getenv("GF2E_TUNE_CACHE");
     if (!path) return;
     FILE* fp = std::fopen(path, "a");
     if (!fp) return;
-    std::fprintf(fp, "{\"arch\": \"gfx950\", \"key\": %llu, \"kernel\": %d, \"name\": \"%s\"}\n",
-                 static_cast<unsigned long long>(key), kind, gemm_name(kind));
+    const int form = choice_form(choice);
+    std::fprintf(fp, "{\"arch\": \"gfx950\", \"key\": %llu, \"choice\": %d, \"form\": \"%s\", \"kernel\": \"%s\"}\n",
+                 static_cast<unsigned long long>(key), choice, form == kFormAlpha ? "alpha" : "schedule",
+                 gemm_name(choice_kind(choice, form)));
     std::fclose(fp);
 }
 
-int Ctx::tune_now(const Plan& p, hipStream_t s)
+int Ctx::exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                   int64_t ldc, hipStream_t s)
 {
-    int rc = ensure_workspace(p.a_bytes + p.b_bytes + p.p_bytes, s);
-    if (rc) return rc;
-    uint64_t* Apl = static_cast<uint64_t*>(ws);
-    uint64_t* Bpl = Apl + p.a_bytes / 8;
-    uint64_t* P = Bpl + p.b_bytes / 8;
-    hipEvent_t e0 = get_event(), e1 = get_event();
-    if (!e0 || !e1) return GF2E_EDEVICE;
-    // Two rounds over all candidates (the first also brings the clocks up);
-    // each candidate keeps its best round.
-    float best_ms[GEMM_NUM_KINDS];
-    for (int kind = 0; kind < GEMM_NUM_KINDS; ++kind) best_ms[kind] = -1.f;
-    const bool verbose = std::getenv("GF2E_TUNE_LOG") != nullptr;
-    for (int round = 0; round < 2; ++round)
-        for (int kind = 0; kind < GEMM_NUM_KINDS; ++kind) {
-            if (launch_gemm(kind, p.T, Apl, Bpl, P, p.m, p.n, p.Mp, p.Np, p.K64p, s) != hipSuccess) {
-                (void)hipGetLastError();
-                continue;  // not applicable to this shape
-            }
-            const int reps = 3;
-            (void)hipEventRecord(e0, s);
-            for (int r = 0; r < reps; ++r)
-                (void)launch_gemm(kind, p.T, Apl, Bpl, P, p.m, p.n, p.Mp, p.Np, p.K64p, s);
-            (void)hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess) return GF2E_EDEVICE;
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= reps;
-            if (verbose)
-                std::fprintf(stderr, "[gf2e tune] T=%d m=%lld k=%lld n=%lld round %d %s %.4f ms\n", p.T,
-                             static_cast<long long>(p.m), static_cast<long long>(p.k),
-                             static_cast<long long>(p.n), round, gemm_name(kind), ms);
-            if (best_ms[kind] < 0 || ms < best_ms[kind]) best_ms[kind] = ms;
-        }
-    int best = -1;
-    for (int kind = 0; kind < GEMM_NUM_KINDS; ++kind)
-        if (best_ms[kind] >= 0 && (best < 0 || best_ms[kind] < best_ms[best])) best = kind;
-    event_pool.push_back(e0);
-    event_pool.push_back(e1);
-    if (best < 0) return GF2E_EDEVICE;
-    const uint64_t key = bucket_key(p.T, p.m, p.k, p.n);
-    tune[key] = best;
-    save_tune_entry(key, best);
-    return GF2E_OK;
-}
-
-int Ctx::run_plan(const Plan& p, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, uint32_t f,
-                  hipStream_t s)
-{
-    int rc = ensure_workspace(p.a_bytes + p.b_bytes + p.p_bytes, s);
-    if (rc) return rc;
-    if (cfg.autotune && forced_kind < 0 && !tune.count(bucket_key(p.T, p.m, p.k, p.n))) {
-        if ((rc = tune_now(p, s))) return rc;
-    }
-    int kind = choose_kind(p);
-    if (!kind_supports(kind, p)) kind = GEMM_MFMA_256x256_W8;  // f32 counts would not be exact
     uint64_t* Apl = static_cast<uint64_t*>(ws);
     uint64_t* Bpl = Apl + p.a_bytes / 8;
     uint64_t* P = Bpl + p.b_bytes / 8;
     hipError_t err;
     {
         StageTimer t(this, GF2E_STAGE_SLICE_A, s);
-        err = launch_slice_rows(p.e, p.sid, A->data, A->ld, p.m, p.k, Apl, p.Mp, p.K64p, d_err, s);
+        err = launch_slice_rows(p.e, p.sid, A, lda, p.m, p.k, Apl, p.Mp, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
         StageTimer t(this, GF2E_STAGE_SLICE_B, s);
-        err = launch_slice_cols(p.e, p.sid, B->data, B->ld, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s);
+        err = p.form == kFormAlpha
+                  ? launch_slice_cols_alpha(p.e, p.f, B, ldb, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s)
+                  : launch_slice_cols(p.e, p.sid, B, ldb, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
         StageTimer t(this, GF2E_STAGE_PRODUCTS, s);
-        err = launch_gemm(kind, p.T, Apl, Bpl, P, p.m, p.n, p.Mp, p.Np, p.K64p, s);
+        err = launch_gemm(kind, p.gT, Apl, Bpl, P, p.m, p.gn, p.Mp, p.gNp, p.gK64p, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
         StageTimer t(this, GF2E_STAGE_COMBINE, s);
-        err = launch_combine(p.e, p.sid, f, P, p.Mp, p.Np / 64, p.m, p.n, C->data, C->ld, s);
+        // Alpha form: result plane c is the column block c of the one product.
+        err = p.form == kFormAlpha
+                  ? launch_combine(p.e, p.sid, p.f, P, p.Np / 64, p.gNp / 64, p.m, p.n, C, ldc, s)
+                  : launch_combine(p.e, p.sid, p.f, P, p.Mp * (p.Np / 64), p.Np / 64, p.m, p.n, C, ldc, s);
     }
-    if (err != hipSuccess) return GF2E_EDEVICE;
+    return err == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+}
+
+int Ctx::tune_now(int e, uint32_t f, int64_t m, int64_t k, int64_t n, hipStream_t s)
+{
+    const Plan plans[kNumForms] = {make_plan(e, f, m, k, n, kFormSchedule), make_plan(e, f, m, k, n, kFormAlpha)};
+    int64_t planes = 0;
+    for (const Plan& p : plans) planes = std::max(planes, p.a_bytes + p.b_bytes + p.p_bytes);
+    const int esz = elem_bytes(e);
+    const int64_t a_in = round_up(m * k * esz, 256), b_in = round_up(k * n * esz, 256);
+    const int64_t c_out = round_up(m * n * esz, 256);
+    int rc = ensure_workspace(planes + a_in + b_in + c_out, s);
+    if (rc) return rc;
+    // Inputs of the timings live in the workspace after the planes: random
+    // field elements (all-zero data runs the matrix cores at lower power and
+    // would time them too fast).
+    uint8_t* in = static_cast<uint8_t*>(ws) + planes;
+    void* dA = in;
+    void* dB = in + a_in;
+    void* dC = in + a_in + b_in;
+    if (launch_fill_elements(dA, m * k, e, 1, s) != hipSuccess ||
+        launch_fill_elements(dB, k * n, e, 2, s) != hipSuccess)
+        return GF2E_EDEVICE;
+    hipEvent_t e0 = get_event(), e1 = get_event();
+    if (!e0 || !e1) return GF2E_EDEVICE;
+    const bool verbose = std::getenv("GF2E_TUNE_LOG") != nullptr;
+    auto timed = [&](auto&& launch, int reps, float* ms) -> bool {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r)
+            if (!launch()) return false;
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) return false;
+        (void)hipEventElapsedTime(ms, e0, e1);
+        *ms /= reps;
+        return true;
+    };
+    int best_kind[kNumForms] = {-1, -1};
+    float pipe_ms[kNumForms] = {-1.f, -1.f};
+    for (int form = 0; form < kNumForms; ++form) {
+        const Plan& p = plans[form];
+        uint64_t* Apl = static_cast<uint64_t*>(ws);
+        uint64_t* Bpl = Apl + p.a_bytes / 8;
+        uint64_t* P = Bpl + p.b_bytes / 8;
+        // Operand planes of this form from the random inputs.
+        if (exec_plan(p, default_kind(p.gT, p.m, p.gn), dA, k, dB, n, dC, n, s) != GF2E_OK) return GF2E_EDEVICE;
+        // Two rounds over all product kernels (the first also brings the
+        // clocks up); each keeps its best round.
+        float best_ms[GEMM_NUM_KINDS];
+        for (int kind = 0; kind < GEMM_NUM_KINDS; ++kind) best_ms[kind] = -1.f;
+        for (int round = 0; round < 2; ++round)
+            for (int kind = 0; kind < GEMM_NUM_KINDS; ++kind) {
+                if (!kind_supports(kind, p)) continue;
+                auto gemm = [&] {
+                    return launch_gemm(kind, p.gT, Apl, Bpl, P, p.m, p.gn, p.Mp, p.gNp, p.gK64p, s) == hipSuccess;
+                };
+                if (!gemm()) {
+                    (void)hipGetLastError();
+                    continue;  // not applicable to this shape
+                }
+                float ms = 0;
+                if (!timed(gemm, 1, &ms)) return GF2E_EDEVICE;
+                if (!timed(gemm, std::clamp(int(1.0f / std::max(ms, 1e-3f)), 3, 100), &ms)) return GF2E_EDEVICE;
+                if (verbose)
+                    std::fprintf(stderr, "[gf2e tune] e=%d m=%lld k=%lld n=%lld form %d round %d %s %.4f ms\n", e,
+                                 static_cast<long long>(m), static_cast<long long>(k), static_cast<long long>(n),
+                                 form, round, gemm_name(kind), ms);
+                if (best_ms[kind] < 0 || ms < best_ms[kind]) best_ms[kind] = ms;
+            }
+        for (int kind = 0; kind < GEMM_NUM_KINDS; ++kind)
+            if (best_ms[kind] >= 0 && (best_kind[form] < 0 || best_ms[kind] < best_ms[best_kind[form]]))
+                best_kind[form] = kind;
+        if (best_kind[form] < 0) continue;
+        // The whole pipeline of this form with its best kernel, repeated
+        // for about 2 ms so that short pipelines are not timed on noise.
+        auto pipe = [&] {
+            return exec_plan(p, best_kind[form], dA, k, dB, n, dC, n, s) == GF2E_OK;
+        };
+        float once = 0;
+        if (!pipe() || !timed(pipe, 1, &once)) return GF2E_EDEVICE;
+        const int reps = std::clamp(int(2.0f / std::max(once, 1e-3f)), 3, 200);
+        if (!timed(pipe, reps, &pipe_ms[form])) return GF2E_EDEVICE;
+        if (verbose)
+            std::fprintf(stderr, "[gf2e tune] e=%d m=%lld k=%lld n=%lld form %d pipeline %s %.4f ms\n", e,
+                         static_cast<long long>(m), static_cast<long long>(k), static_cast<long long>(n), form,
+                         gemm_name(best_kind[form]), pipe_ms[form]);
+    }
+    event_pool.push_back(e0);
+    event_pool.push_back(e1);
+    if (best_kind[kFormSchedule] < 0 && best_kind[kFormAlpha] < 0) return GF2E_EDEVICE;
+    int form = kFormSchedule;
+    if (best_kind[kFormSchedule] < 0 || (best_kind[kFormAlpha] >= 0 && pipe_ms[kFormAlpha] < pipe_ms[kFormSchedule]))
+        form = kFormAlpha;
+    const int choice = pack_choice(best_kind[kFormSchedule] < 0 ? 0xFF : best_kind[kFormSchedule],
+                                   best_kind[kFormAlpha] < 0 ? 0xFF : best_kind[kFormAlpha], form);
+    const uint64_t key = bucket_of(e, f, m, k, n);
+    tune[key] = choice;
+    save_tune_entry(key, choice);
     return GF2E_OK;
+}
+
+int Ctx::mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, hipStream_t s)
+{
+    const int64_t m = A->rows, k = A->cols, n = B->cols;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cs);
+    int rc;
+    if (cfg.autotune && (forced_kind < 0 || forced_form < 0) && cs == hipStreamCaptureStatusNone &&
+        !tune.count(bucket_of(e, f, m, k, n))) {
+        if ((rc = tune_now(e, f, m, k, n, s))) return rc;
+    }
+    const Plan p = make_plan(e, f, m, k, n, choose_form(e, f, m, k, n));
+    int kind = choose_kind(p);
+    if (!kind_supports(kind, p)) kind = GEMM_MFMA_256x256_W8;  // f32 counts would not be exact
+    if ((rc = ensure_workspace(p.a_bytes + p.b_bytes + p.p_bytes, s))) return rc;
+    return exec_plan(p, kind, A->data, A->ld, B->data, B->ld, C->data, C->ld, s);
 }
 
 }  // namespace gf2e
@@ -466,8 +571,7 @@ int gf2e_mul_async(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_
         c->mark_used(s);
         return GF2E_OK;
     }
-    const Plan p = make_plan(e, f, m, k, n);
-    rc = c->run_plan(p, A, B, C, f, s);
+    rc = c->mul(e, f, A, B, C, s);
     c->mark_used(s);
     return rc;
 }
@@ -566,8 +670,8 @@ int gf2e_combine(gf2e_ctx* handle, int e, uint32_t f, const uint64_t* p_planes, 
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageTimer t(c, GF2E_STAGE_COMBINE, s);
-    return launch_combine(e, schedule_id(e, f), f, p_planes, Mp, Np / 64, C->rows, C->cols, C->data, C->ld,
-                          s) ==
+    return launch_combine(e, schedule_id(e, f), f, p_planes, Mp * (Np / 64), Np / 64, C->rows, C->cols, C->data,
+                          C->ld, s) ==
                    hipSuccess
                ? GF2E_OK
                : GF2E_EDEVICE;
@@ -590,7 +694,25 @@ int gf2e_chosen_kernel(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c) return GF2E_EINVAL;
     if (!field_ok(e, f)) return GF2E_EFIELD;
-    return c->choose_kind(make_plan(e, f, m, k, n));
+    const Plan p = make_plan(e, f, m, k, n, c->choose_form(e, f, m, k, n));
+    const int kind = c->choose_kind(p);
+    return kind_supports(kind, p) ? kind : GEMM_MFMA_256x256_W8;
+}
+
+int gf2e_set_form(gf2e_ctx* handle, int form)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c || form < GF2E_FORM_AUTO || form >= kNumForms) return GF2E_EINVAL;
+    c->forced_form = form;
+    return GF2E_OK;
+}
+
+int gf2e_chosen_form(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k, int64_t n)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c) return GF2E_EINVAL;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
+    return c->choose_form(e, f, m, k, n);
 }
 
 int gf2e_tune(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k, int64_t n, void* stream)
@@ -602,7 +724,7 @@ int gf2e_tune(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k, int64_t
     DeviceGuard guard(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     c->order_stream(s);
-    int rc = c->tune_now(make_plan(e, f, m, k, n), s);
+    int rc = c->tune_now(e, f, m, k, n, s);
     c->mark_used(s);
     return rc;
 }

@@ -23,13 +23,26 @@ private:
     int prev_ = -1;
 };
 
+// How the plain path computes one product.  kFormSchedule: T GF(2) plane
+// products of the bilinear schedule (Section 5), then recombination and
+// reduction.  kFormAlpha: one GF(2) product of the e A-planes (m x ek) with
+// the ek x en matrix of the planes of alpha^i B (reduction folded in), then
+// clinging of its e result planes; e^2 bit products per element product
+// instead of T, but a single larger launch and no recombination.
+enum Form : int { kFormSchedule = 0, kFormAlpha = 1, kNumForms = 2 };
+
 // Sizes of one product's planes (see the layout notes in gf2e_internal.hpp).
 struct Plan {
     int e = 0, T = 0;
-    int sid = -1;  // schedule: < 0 Karatsuba + run-time reduction, else field schedule
+    int form = kFormSchedule;
+    int sid = -1;  // schedule: -1 Karatsuba + run-time reduction, >= 0 field schedule, -2 identity
     uint32_t f = 0;
     int64_t m = 0, k = 0, n = 0;
     int64_t Mp = 0, Np = 0, K64p = 0;
+    // Geometry of the product launch: gT planes of an m x gn result with
+    // padded width gNp and gK64p words of k.
+    int gT = 0;
+    int64_t gn = 0, gNp = 0, gK64p = 0;
     int64_t a_bytes = 0, b_bytes = 0, p_bytes = 0;
 };
 
@@ -41,7 +54,7 @@ int validate_mul(const gf2e_mat* A, const gf2e_mat* B, const gf2e_mat* C, int e,
 // Schedule for (e, f): the field schedule if one is compiled in (and not
 // disabled with GF2E_SCHEDULE=karatsuba), else -1.
 int schedule_id(int e, uint32_t f);
-Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n);
+Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form = kFormSchedule);
 int default_kind(int T, int64_t m, int64_t n);
 bool kind_supports(int kind, const Plan& p);
 
@@ -51,6 +64,7 @@ struct Ctx {
     int device = 0;
     gf2e_config cfg{};
     int forced_kind = -1;
+    int forced_form = -1;  // GF2E_FORM_AUTO
     int* d_err = nullptr;  // sticky device flag: an entry >= 2^e was seen
 
     void* ws = nullptr;  // plane workspace of the plain path
@@ -65,7 +79,8 @@ struct Ctx {
     int64_t prof_n[GF2E_NUM_STAGES] = {};
     std::vector<hipEvent_t> event_pool;
 
-    std::map<uint64_t, int> tune;  // size bucket -> product kernel
+    // size bucket -> tuned choice: product kernel | (form << 8)
+    std::map<uint64_t, int> tune;
 
     std::vector<BatchGraph*> batches;  // cached batched graphs (owned), least recent first
     int64_t batch_threshold = 384;     // min(m, n) at which a product takes 256x256 tiles
@@ -77,12 +92,18 @@ struct Ctx {
     void order_stream(hipStream_t s);
     void mark_used(hipStream_t s);
     int ensure_workspace(int64_t bytes, hipStream_t s);
+    // Form and product kernel for a product (forced, tuned or default).
+    int choose_form(int e, uint32_t f, int64_t m, int64_t k, int64_t n);
     int choose_kind(const Plan& p);
-    int tune_now(const Plan& p, hipStream_t s);
+    // Times the product kernels for the plans of both forms and then both
+    // whole pipelines (on inputs it allocates), and records the faster.
+    int tune_now(int e, uint32_t f, int64_t m, int64_t k, int64_t n, hipStream_t s);
     void load_tune_cache();
-    void save_tune_entry(uint64_t key, int kind);
-    int run_plan(const Plan& p, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, uint32_t f,
-                 hipStream_t s);
+    void save_tune_entry(uint64_t key, int choice);
+    int mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, hipStream_t s);
+    // Launches the stages of plan p with product kernel kind; planes in ws.
+    int exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const void* B, int64_t ldb,
+                  void* C, int64_t ldc, hipStream_t s);
     void release_batches();
 };
 

@@ -62,9 +62,14 @@ hipError_t launch_slice_cols(int e, int sid, const void* B, int64_t ldb, int64_t
 hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P,
                        int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t K64p,
                        hipStream_t s);
+// Alpha-power form: slice columns of B into the Ek x En operand whose block
+// (i, c) is plane c of alpha^i B (block rows of K64p words, row pitch E*Np).
+hipError_t launch_slice_cols_alpha(int e, uint32_t f, const void* B, int64_t ldb, int64_t k, int64_t n,
+                                   uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s);
 // Recombine the T products into result planes (reducing mod f for Karatsuba
-// schedules) and write C (m x n elements).
-hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
+// schedules) and write C (m x n elements).  Product s, row i, word w is at
+// P[s*pstride + i*ldp + w] (pstride = Mp*ldp for the grouped layout above).
+hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t pstride, int64_t ldp,
                           int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s);
 // One product of a batch, as the batched kernels read it from device memory.
 struct BatchProduct {
@@ -102,6 +107,8 @@ hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const Wor
 int persistent_grid(int kind);  // workgroups that fill the device once
 hipError_t launch_reset_counters(int* counters, int n, hipStream_t s);
 
+// count pseudo-random elements of F_{2^e} (uint8 for e <= 8, else uint16).
+hipError_t launch_fill_elements(void* X, int64_t count, int e, uint64_t seed, hipStream_t s);
 // C = 0 (the k = 0 product).
 hipError_t launch_zero(void* C, int64_t rows, int64_t cols, int64_t ld, int elem_bytes,
                        hipStream_t s);

@@ -192,11 +192,15 @@ constexpr int num_products(int e) { return best_count(e); }
 
 namespace gf2e {
 
-// The schedule a set of kernels runs.  sid < 0: the Karatsuba schedule for
+// The schedule a set of kernels runs.  sid = -1: the Karatsuba schedule for
 // e, whose 2e-1 coefficient planes w are reduced modulo f at run time.
 // sid >= 0: kFieldSchedules[sid], a schedule for one field with the reduction
 // folded in, so that result plane c is the XOR of the products s with c in
 // c[s].  u and v are the operand subsets of the A and B sides.
+// sid = kIdentitySchedule: t = e, operand s is bit-plane s and result plane s
+// is product s; the alpha-power form uses it to slice A into its bit-planes
+// and to cling its e result planes.
+constexpr int kIdentitySchedule = -2;
 struct KernelSchedule {
     int e = 0;
     int t = 0;
@@ -208,7 +212,12 @@ struct KernelSchedule {
 constexpr KernelSchedule kernel_schedule(int e, int sid)
 {
     KernelSchedule k{};
-    if (sid < 0) {
+    if (sid == kIdentitySchedule) {
+        k.e = e;
+        k.t = e;
+        k.folded = true;
+        for (int s = 0; s < e; ++s) k.u[s] = k.v[s] = k.c[s] = 1u << s;
+    } else if (sid < 0) {
         const Schedule S = build_schedule(e);
         k.e = e;
         k.t = S.t;

@@ -9,6 +9,7 @@
 // bytes and plane words with 8x8 bit-matrix transposes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "gf2e_device.hpp"
@@ -109,12 +110,12 @@ __device__ __attribute__((always_inline)) inline void slice_row_word(const void*
     store_operands<E, SID, false>(pl, planes + kw * Mp + r, K64p * Mp);
 }
 
-// Column slicing of one plane word: column j of B, k-bits [64kw, 64kw+64).
+// Bit-planes of one column word: column j of B, k-bits [64kw, 64kw+64).
 // Consecutive threads take consecutive columns, so every load is coalesced.
-template <int E, int SID>
-__device__ __attribute__((always_inline)) inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
-                                      uint64_t* __restrict__ planes, int64_t Np, int64_t K64p,
-                                      int* __restrict__ err, int64_t j, int64_t kw)
+template <int E>
+__device__ __attribute__((always_inline)) inline void load_col_planes(const void* __restrict__ B, int64_t ldb,
+                                                                       int64_t k, int64_t n, int* __restrict__ err,
+                                                                       int64_t j, int64_t kw, uint64_t (&pl)[E])
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     uint64_t lo[8] = {}, hi[8] = {};
@@ -134,24 +135,68 @@ __device__ __attribute__((always_inline)) inline void slice_col_word(const void*
         }
     }
     if (bad) atomicOr(err, 1);
-    uint64_t pl[E];
     bytes_to_planes<E>(lo, hi, pl);
+}
+
+// Column slicing of one plane word into the schedule's B-side operands.
+template <int E, int SID>
+__device__ __attribute__((always_inline)) inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
+                                      uint64_t* __restrict__ planes, int64_t Np, int64_t K64p,
+                                      int* __restrict__ err, int64_t j, int64_t kw)
+{
+    uint64_t pl[E];
+    load_col_planes<E>(B, ldb, k, n, err, j, kw, pl);
     store_operands<E, SID, true>(pl, planes + kw * Np + j, K64p * Np);
 }
 
+// Alpha-power slicing of one column word (alpha = x, the class of x in
+// F_2[x]/<f>).  With C_c = sum_i A_i * (plane c of alpha^i B), the product
+// becomes one GF(2) product of [A_0 .. A_{E-1}] (m x Ek) with the Ek x En
+// matrix whose block (i, c) is plane c of alpha^i B; the reduction modulo f
+// is folded into that matrix.  Block (i, c), word (kw, j) is stored at
+// planes[(i*K64p + kw)*E*Np + c*Np + j].  alpha^(i+1) B = x * alpha^i B on
+// bit-planes: shift up by one and fold the plane that leaves back in with f.
+template <int E>
+__device__ __attribute__((always_inline)) inline void slice_col_word_alpha(const void* __restrict__ B, int64_t ldb,
+                                                                            int64_t k, int64_t n, uint32_t f,
+                                                                            uint64_t* __restrict__ planes, int64_t Np,
+                                                                            int64_t K64p, int* __restrict__ err,
+                                                                            int64_t j, int64_t kw)
+{
+    uint64_t cur[E];
+    load_col_planes<E>(B, ldb, k, n, err, j, kw, cur);
+    uint64_t fm[E];
+#pragma unroll
+    for (int b = 0; b < E; ++b) fm[b] = 0ull - uint64_t((f >> b) & 1u);
+    const int64_t ld = int64_t(E) * Np;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        uint64_t* row = planes + (int64_t(i) * K64p + kw) * ld + j;
+#pragma unroll
+        for (int c = 0; c < E; ++c) row[int64_t(c) * Np] = cur[c];
+        if (i + 1 < E) {
+            const uint64_t top = cur[E - 1];
+#pragma unroll
+            for (int b = E - 1; b > 0; --b) cur[b] = cur[b - 1] ^ (top & fm[b]);
+            cur[0] = top & fm[0];
+        }
+    }
+}
+
 // Combine of one word: word w of row i of every product plane becomes 64
-// elements of C.  k0 set: the product has an empty inner dimension, C = 0.
+// elements of C.  Product s, row i, word w is at P[s*pstride + i*ldp + w].
+// k0 set: the product has an empty inner dimension, C = 0.
 template <int E, int SID>
-__device__ __attribute__((always_inline)) inline void combine_word(const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp,
-                                    int64_t n, uint32_t f, void* __restrict__ C, int64_t ldc,
-                                    int64_t i, int64_t w, bool k0)
+__device__ __attribute__((always_inline)) inline void combine_word(const uint64_t* __restrict__ P, int64_t pstride,
+                                    int64_t ldp, int64_t n, uint32_t f, void* __restrict__ C,
+                                    int64_t ldc, int64_t i, int64_t w, bool k0)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     constexpr KernelSchedule S = kernel_schedule(E, SID);
     constexpr int D = 2 * E - 1;
     uint64_t p[S.t];
 #pragma unroll
-    for (int s = 0; s < S.t; ++s) p[s] = k0 ? 0ull : P[s * Mp * ldp + i * ldp + w];
+    for (int s = 0; s < S.t; ++s) p[s] = k0 ? 0ull : P[s * pstride + i * ldp + w];
 
     uint64_t c[D];
     if constexpr (S.folded) {
@@ -247,16 +292,26 @@ __global__ __launch_bounds__(kThreads) void slice_cols_kernel(
     slice_col_word<E, SID>(B, ldb, k, n, planes, Np, K64p, err, j, blockIdx.y);
 }
 
+template <int E>
+__global__ __launch_bounds__(kThreads) void slice_cols_alpha_kernel(
+    const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint32_t f, uint64_t* __restrict__ planes,
+    int64_t Np, int64_t K64p, int* __restrict__ err)
+{
+    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (j >= Np) return;
+    slice_col_word_alpha<E>(B, ldb, k, n, f, planes, Np, K64p, err, j, blockIdx.y);
+}
+
 template <int E, int SID>
 __global__ __launch_bounds__(kThreads) void combine_kernel(
-    const uint64_t* __restrict__ P, int64_t Mp, int64_t ldp, int64_t m, int64_t n, uint32_t f,
+    const uint64_t* __restrict__ P, int64_t pstride, int64_t ldp, int64_t m, int64_t n, uint32_t f,
     void* __restrict__ C, int64_t ldc)
 {
     const int64_t nw = (n + 63) / 64;
     const int64_t w = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (w >= nw) return;
     for (int64_t i = blockIdx.y; i < m; i += gridDim.y)
-        combine_word<E, SID>(P, Mp, ldp, n, f, C, ldc, i, w, false);
+        combine_word<E, SID>(P, pstride, ldp, n, f, C, ldc, i, w, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,6 +334,29 @@ __host__ __device__ inline bool with_field_schedule(int sid, Fn& fn)
     }
 }
 
+// Calls fn.template operator()<E>() for e = 2..10.
+template <class Fn>
+__host__ __device__ inline bool with_e(int e, Fn&& fn)
+{
+    switch (e) {
+        case 2: fn.template operator()<2>(); return true;
+        case 3: fn.template operator()<3>(); return true;
+        case 4: fn.template operator()<4>(); return true;
+        case 5: fn.template operator()<5>(); return true;
+        case 6: fn.template operator()<6>(); return true;
+        case 7: fn.template operator()<7>(); return true;
+        case 8: fn.template operator()<8>(); return true;
+        case 9: fn.template operator()<9>(); return true;
+        case 10: fn.template operator()<10>(); return true;
+        default: return false;
+    }
+}
+
+// As with_schedule, and sid = kIdentitySchedule too (host launches only, so
+// the batched kernels do not carry the identity instantiations).
+template <class Fn>
+inline bool with_any_schedule(int e, int sid, Fn&& fn);
+
 template <class Fn>
 __host__ __device__ inline bool with_schedule(int e, int sid, Fn&& fn)
 {
@@ -295,6 +373,14 @@ __host__ __device__ inline bool with_schedule(int e, int sid, Fn&& fn)
         case 10: fn.template operator()<10, -1>(); return true;
         default: return false;
     }
+}
+
+template <class Fn>
+inline bool with_any_schedule(int e, int sid, Fn&& fn)
+{
+    if (sid == kIdentitySchedule)
+        return with_e(e, [&]<int E>() { fn.template operator()<E, kIdentitySchedule>(); });
+    return with_schedule(e, sid, fn);
 }
 
 __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProduct* __restrict__ prods,
@@ -329,8 +415,25 @@ __global__ __launch_bounds__(kThreads) void batched_combine_kernel(const BatchPr
     if (idx >= P.m * nw) return;
     const int64_t i = idx / nw, w = idx % nw;
     with_schedule(P.e, P.sid, [&]<int E, int SID>() {
-        combine_word<E, SID>(P.P, P.Mp, P.Np / 64, P.n, P.f, P.C, P.ldc, i, w, P.k == 0);
+        combine_word<E, SID>(P.P, P.Mp * (P.Np / 64), P.Np / 64, P.n, P.f, P.C, P.ldc, i, w, P.k == 0);
     });
+}
+
+// Pseudo-random field elements (a 64-bit mix of the index and the seed,
+// masked to e bits), used as tuning inputs so the timed kernels see data of
+// realistic density.
+__global__ void fill_elements_kernel(void* X, int64_t count, int elem_bytes, uint32_t mask, uint64_t seed)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        uint64_t z = uint64_t(i) + seed * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const uint32_t v = uint32_t(z) & mask;
+        if (elem_bytes == 1) static_cast<uint8_t*>(X)[i] = uint8_t(v);
+        else static_cast<uint16_t*>(X)[i] = uint16_t(v);
+    }
 }
 
 __global__ void zero_kernel(uint8_t* C, int64_t rows, int64_t row_bytes, int64_t ld_bytes)
@@ -348,7 +451,7 @@ hipError_t launch_slice_rows(int e, int sid, const void* A, int64_t lda, int64_t
 {
     if (Mp <= 0 || K64p <= 0) return hipSuccess;
     dim3 grid(unsigned(ceil_div(Mp, kThreads)), unsigned(K64p));
-    if (!with_schedule(e, sid, [&]<int E, int SID>() {
+    if (!with_any_schedule(e, sid, [&]<int E, int SID>() {
             hipLaunchKernelGGL((slice_rows_kernel<E, SID>), grid, dim3(kThreads), 0, s, A, lda, m, k, planes,
                                Mp, K64p, err);
         }))
@@ -369,16 +472,38 @@ hipError_t launch_slice_cols(int e, int sid, const void* B, int64_t ldb, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t Mp, int64_t ldp,
+hipError_t launch_slice_cols_alpha(int e, uint32_t f, const void* B, int64_t ldb, int64_t k, int64_t n,
+                                   uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s)
+{
+    if (Np <= 0 || K64p <= 0) return hipSuccess;
+    dim3 grid(unsigned(ceil_div(Np, kThreads)), unsigned(K64p));
+    if (!with_e(e, [&]<int E>() {
+            hipLaunchKernelGGL((slice_cols_alpha_kernel<E>), grid, dim3(kThreads), 0, s, B, ldb, k, n, f,
+                               planes, Np, K64p, err);
+        }))
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t pstride, int64_t ldp,
                           int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
     dim3 grid(unsigned(ceil_div(ceil_div(n, 64), kThreads)), unsigned(m < 65535 ? m : 65535));
-    if (!with_schedule(e, sid, [&]<int E, int SID>() {
-            hipLaunchKernelGGL((combine_kernel<E, SID>), grid, dim3(kThreads), 0, s, P, Mp, ldp, m, n, f, C,
-                               ldc);
+    if (!with_any_schedule(e, sid, [&]<int E, int SID>() {
+            hipLaunchKernelGGL((combine_kernel<E, SID>), grid, dim3(kThreads), 0, s, P, pstride, ldp, m, n, f,
+                               C, ldc);
         }))
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_elements(void* X, int64_t count, int e, uint64_t seed, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(ceil_div(count, 256), 8192);
+    hipLaunchKernelGGL(fill_elements_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, X, count, e <= 8 ? 1 : 2,
+                       (1u << e) - 1u, seed);
     return hipGetLastError();
 }
 

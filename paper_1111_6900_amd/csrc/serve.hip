@@ -265,7 +265,7 @@ bool Server::issue_iteration()
         if (r->d.k == 0)
             (void)launch_zero(r->d.C, r->d.m, r->d.n, r->d.ldc, elem_bytes(r->d.e), stream);
         else
-            (void)launch_combine(r->d.e, r->d.sid, r->d.f, r->d.P, r->d.Mp, r->d.Np / 64, r->d.m, r->d.n, r->d.C,
+            (void)launch_combine(r->d.e, r->d.sid, r->d.f, r->d.P, r->d.Mp * (r->d.Np / 64), r->d.Np / 64, r->d.m, r->d.n, r->d.C,
                                  r->d.ldc, stream);
         (void)hipMemcpyAsync(h_err + r->slot, d_err + r->slot, sizeof(int), hipMemcpyDeviceToHost, stream);
         (void)launch_reset_counters(d_err + r->slot, 1, stream);

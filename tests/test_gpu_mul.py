@@ -73,6 +73,73 @@ def test_every_product_kernel(g, e, kind):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def actx(g):
+    """A context that always takes the alpha-power form."""
+    c = g.Context(0)
+    c.set_form(g.FORM_ALPHA)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("e,f", ALL_E + [(4, 0x1F), (8, 0x11B)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 4), (63, 65, 64), (129, 127, 130), (257, 300, 255)])
+def test_alpha_form_small_shapes(actx, e, f, shape):
+    m, k, n = shape
+    print(f"alpha form e={e} f={f:#x} shape={shape}", flush=True)
+    gen = np.random.default_rng(e * 17 + m * 3 + k)
+    A = workload.field_matrix(gen, m, k, e)
+    B = workload.field_matrix(gen, k, n, e)
+    assert (gpu_mul(actx, A, B, e, f) == oracle.matmul(A, B, e, f)).all()
+
+
+@pytest.mark.parametrize("kind", list(range(8)))
+@pytest.mark.parametrize("e", [2, 4, 7])
+def test_alpha_form_every_kernel(g, e, kind):
+    f = workload.DEFAULT_POLY[e]
+    print(f"alpha form kernel {kind} e={e}", flush=True)
+    c = g.Context(0, kernel=kind)
+    c.set_form(g.FORM_ALPHA)
+    gen = np.random.default_rng(kind * 10 + e + 1000)
+    A = workload.field_matrix(gen, 300, 517, e)
+    B = workload.field_matrix(gen, 517, 270, e)
+    assert c.chosen_form(e, f, 300, 517, 270) == g.FORM_ALPHA
+    assert (gpu_mul(c, A, B, e, f) == oracle.matmul(A, B, e, f)).all()
+    c.close()
+
+
+def test_alpha_form_falls_back_from_fp4_past_its_count_limit(g):
+    """The alpha form's product has e*k bits of inner dimension, so the fp4
+    kernels (exact below 2^24) are replaced by the int8 kernel earlier."""
+    c = g.Context(0, kernel=g.KERNEL_FP4_128)
+    k = 2**22 + 1
+    assert c.chosen_kernel(4, 0x13, 64, k, 64) == g.KERNEL_FP4_128
+    c.set_form(g.FORM_ALPHA)
+    assert c.chosen_kernel(4, 0x13, 64, k, 64) == g.KERNEL_MFMA_256_W8
+    assert c.chosen_kernel(4, 0x13, 64, 2**21, 64) == g.KERNEL_FP4_128
+    c.close()
+
+
+def test_autotuned_form_is_exact_and_leaves_inputs_alone(g):
+    c = g.Context(0, autotune=True)
+    for name in ["f4_256"]:
+        e, f, A, B = workload.plain_inputs(name)
+        m, k, n = A.shape[0], A.shape[1], B.shape[1]
+        Ad, Bd = dev(A, e), dev(B, e)
+        c.tune(e, f, m, k, n)
+        form = c.chosen_form(e, f, m, k, n)
+        print(f"{name}: tuned form {form}, kernel {c.chosen_kernel(e, f, m, k, n)}", flush=True)
+        assert form in (g.FORM_SCHEDULE, g.FORM_ALPHA)
+        assert (host(Ad) == A).all() and (host(Bd) == B).all()
+        assert (host(c.mul(Ad, Bd, e, f)) == oracle.matmul(A, B, e, f)).all()
+        # forcing either form after tuning keeps the result
+        for fm in (g.FORM_SCHEDULE, g.FORM_ALPHA):
+            c.set_form(fm)
+            assert (host(c.mul(Ad, Bd, e, f)) == oracle.matmul(A, B, e, f)).all()
+        c.set_form(g.FORM_AUTO)
+    c.close()
+
+
 def test_brute_force_all_2x2_over_f4(ctx):
     mats = np.array(np.meshgrid(*[np.arange(4)] * 4, indexing="ij")).reshape(4, -1).T.reshape(-1, 2, 2)
     A = mats.reshape(-1, 2)
@@ -254,6 +321,10 @@ def _full_size_check(ctx, name, kinds, nrows=4, nsamp=4096):
 
 def test_config_f16_4096_sampled(ctx):
     _full_size_check(ctx, "f16_4096", [-1, 0, 4, 5, 6])
+
+
+def test_config_f16_4096_sampled_alpha_form(actx):
+    _full_size_check(actx, "f16_4096", [-1, 5, 7])
 
 
 def test_config_f256_8192_sampled(ctx):
