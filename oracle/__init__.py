@@ -65,6 +65,7 @@ def _load():
                                           vp, i64, i32]
     lib.gf2e_oracle_freivalds.restype = i64
     lib.gf2e_oracle_max_threads.restype = i32
+    lib.gf2e_oracle_trsm.argtypes = [i32, u32, i32, i32, i64, i64, vp, i64, vp, i64, i32]
     _lib = lib
     return lib
 
@@ -178,6 +179,20 @@ def freivalds(A, B, C, e: int, f: int, R, nthreads: int = 0) -> int:
     if rc < 0:
         raise OracleError(f"oracle returned error code {rc}")
     return int(rc)
+
+
+def trsm(T, B, e: int, f: int, lower: bool = False, unit: bool = False, nthreads: int = 0) -> np.ndarray:
+    """X with T X = B for triangular T (Section 4.3's row algorithm); B is
+    not modified.  Raises OracleError(-9) for a zero on the diagonal."""
+    T = _as_field_matrix(T, e)
+    X = _as_field_matrix(B, e).copy()
+    m = T.shape[0]
+    if T.shape != (m, m) or X.shape[0] != m:
+        raise ValueError("shape mismatch")
+    n = X.shape[1]
+    _check(_load().gf2e_oracle_trsm(e, f, 1 if lower else 0, 1 if unit else 0, m, n, _ptr(T), m,
+                                    _ptr(X), n, nthreads))
+    return X
 
 
 def max_threads() -> int:

@@ -32,6 +32,7 @@
 #define ORC_EFIELD (-2)
 #define ORC_EINVAL (-1)
 #define ORC_ERANGE (-5)
+#define ORC_ESINGULAR (-9)
 
 /* ---------------------------------------------------------------------- */
 /* Polynomials over F_2, held in the bits of an unsigned integer.           */
@@ -312,3 +313,68 @@ int64_t gf2e_oracle_freivalds(int e, uint32_t f, int64_t m, int64_t k, int64_t n
 }
 
 int gf2e_oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/* ---------------------------------------------------------------------- */
+/* Triangular solving (Section 4.3).                                       */
+/* ---------------------------------------------------------------------- */
+
+/* X = T^{-1} B for a triangular m x m matrix T, overwriting B (m x n).
+ *
+ * Upper T (lower = 0), the algorithm of Section 4.3: for i from m-1 down to
+ * 0, scale row i of B by the inverse of T[i][i], then add T[j][i] times that
+ * row to every row j < i.  Lower T (lower = 1) is the mirror image: rows from
+ * 0 up, and the scaled row i is added to every row j > i with factor T[j][i].
+ * unit = 1 takes the diagonal as ones (its entries are not read).  Columns
+ * are independent, so column ranges are split across nthreads threads.
+ *
+ * ORC_ESINGULAR if a diagonal entry is zero (unit = 0); ORC_ERANGE if an
+ * entry that is read is not below 2^e (B is then left partly solved). */
+int gf2e_oracle_trsm(int e, uint32_t f, int lower, int unit, int64_t m, int64_t n,
+                     const void* Tm, int64_t ldt, void* B, int64_t ldb, int nthreads)
+{
+    if (m < 0 || n < 0) return ORC_EINVAL;
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc != ORC_OK) { free(T); return rc; }
+    const int wide = e > 8;
+    const uint32_t lim = 1u << e;
+    /* Check the triangle that is read, and the diagonal, first. */
+    for (int64_t i = 0; i < m && rc == ORC_OK; ++i) {
+        for (int64_t j = lower ? 0 : i; j < (lower ? i + 1 : m); ++j) {
+            if (j == i && unit) continue;
+            const uint32_t t = get_el(Tm, wide, i * ldt + j);
+            if (t >= lim) { rc = ORC_ERANGE; break; }
+            if (j == i && t == 0) { rc = ORC_ESINGULAR; break; }
+        }
+    }
+    if (rc == ORC_OK && !all_in_field(B, wide, m, n, ldb, lim)) rc = ORC_ERANGE;
+    if (rc != ORC_OK) { free(T); return rc; }
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+    const int64_t chunk = 64;
+
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+        for (int64_t step = 0; step < m; ++step) {
+            const int64_t i = lower ? step : m - 1 - step;
+            if (!unit) {
+                /* inverse of T[i][i] = g^(q - log T[i][i]) */
+                const uint32_t d = get_el(Tm, wide, i * ldt + i);
+                const uint32_t dinv = T->exp[T->q - T->log[d]];
+                for (int64_t j = c0; j < c1; ++j)
+                    put_el(B, wide, i * ldb + j, tab_mul(T, dinv, get_el(B, wide, i * ldb + j)));
+            }
+            const int64_t r0 = lower ? i + 1 : 0, r1 = lower ? m : i;
+            for (int64_t r = r0; r < r1; ++r) {
+                const uint32_t x = get_el(Tm, wide, r * ldt + i);
+                if (!x) continue;
+                for (int64_t j = c0; j < c1; ++j)
+                    put_el(B, wide, r * ldb + j,
+                           get_el(B, wide, r * ldb + j) ^ tab_mul(T, x, get_el(B, wide, i * ldb + j)));
+            }
+        }
+    }
+    free(T);
+    return ORC_OK;
+}
