@@ -53,7 +53,8 @@ enum {
     GF2E_ERANGE = -5,  /* an input entry is >= 2^e (found on the device) */
     GF2E_ENOMEM = -6,  /* workspace could not be allocated or exceeds the limit */
     GF2E_EDEVICE = -7, /* a HIP runtime call failed */
-    GF2E_EBUSY = -8    /* serving: request does not fit the memory budget right now */
+    GF2E_EBUSY = -8,   /* serving: request does not fit the memory budget right now */
+    GF2E_ESINGULAR = -9 /* triangular solve: a zero on the diagonal (found on the device) */
 };
 
 typedef struct gf2e_ctx gf2e_ctx;
@@ -177,9 +178,31 @@ int gf2e_server_run_trace(gf2e_server* srv, int count, const gf2e_mat* A, const 
 int gf2e_mul(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
              uint32_t f);
 
-/* Wait for `stream`; return GF2E_ERANGE (once) if any product enqueued since
- * the previous sync found an entry >= 2^e, else GF2E_OK. */
+/* Wait for `stream`; return GF2E_ERANGE (once) if any call enqueued since
+ * the previous sync found an entry >= 2^e, else GF2E_ESINGULAR (once) if a
+ * triangular solve found a zero on its diagonal, else GF2E_OK. */
 int gf2e_sync(gf2e_ctx* ctx, void* stream);
+
+/* C += A * B over F_{2^e} (the accumulating form of gf2e_mul_async; the
+ * combine step adds to C instead of replacing it).  Same rules as
+ * gf2e_mul_async; k = 0 leaves C unchanged. */
+int gf2e_mul_add_async(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
+                       uint32_t f, void* stream);
+int gf2e_mul_add(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e, uint32_t f);
+
+/* Triangular solving with matrices (Section 4.3): B <- T^{-1} B, where T is
+ * an m x m upper (lower = 0) or lower (lower = 1) triangular matrix and B is
+ * m x n.  Only T's triangle is read; unit = 1 takes its diagonal as ones
+ * (the diagonal entries are then not read).  The diagonal 128 x 128 blocks
+ * of T are inverted on the device, and the remaining work is gf2e products
+ * (C += A*B) over a recursion on block ranges.  B must not overlap T
+ * (GF2E_EALIAS).  A zero on a non-unit diagonal is reported by gf2e_sync as
+ * GF2E_ESINGULAR (B is then unspecified).  The context's triangular-solve
+ * buffers (inverted blocks and one block row of B) are owned by the
+ * context.  Enqueued on `stream`. */
+int gf2e_trsm_async(gf2e_ctx* ctx, int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e,
+                    uint32_t f, void* stream);
+int gf2e_trsm(gf2e_ctx* ctx, int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f);
 
 const char* gf2e_strerror(int code);
 

@@ -16,7 +16,8 @@ import torch  # loads the HIP runtime the library then shares
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgf2e.so")
 
-OK, EINVAL, EFIELD, ESHAPE, EALIAS, ERANGE, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+OK, EINVAL, EFIELD, ESHAPE, EALIAS, ERANGE, ENOMEM, EDEVICE, EBUSY, ESINGULAR = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 KERNEL_AUTO, KERNEL_MFMA_256, KERNEL_MFMA_128, KERNEL_MFMA_256x128, KERNEL_MFMA_64, KERNEL_VALU_128, \
     KERNEL_MFMA_256_W8, KERNEL_FP4_256_W8, KERNEL_FP4_128 = -1, 0, 1, 2, 3, 4, 5, 6, 7
 FORM_AUTO, FORM_SCHEDULE, FORM_ALPHA = -1, 0, 1
@@ -81,6 +82,10 @@ _SIGS = {
     "gf2e_mul": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
     "gf2e_mul_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
     "gf2e_sync": (_i32, [_vp, _vp]),
+    "gf2e_mul_add_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
+    "gf2e_mul_add": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
+    "gf2e_trsm_async": (_i32, [_vp, _i32, _i32, _P(Mat), _P(Mat), _i32, _u32, _vp]),
+    "gf2e_trsm": (_i32, [_vp, _i32, _i32, _P(Mat), _P(Mat), _i32, _u32]),
     "gf2e_mul_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_set_batch_threshold": (_i32, [_vp, _i64]),
     "gf2e_tune_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -262,6 +267,36 @@ class Context:
         out = self.mul_async(A, B, e, f, out=out, stream=stream)
         self.sync(stream)
         return out
+
+    def mul_add_async(self, A, B, C, e: int, f: int, stream=None):
+        """C += A * B (in place)."""
+        _check_elem(A, e, "A")
+        _check_elem(B, e, "B")
+        _check_elem(C, e, "C")
+        a, b, c = mat(A), mat(B), mat(C)
+        _check(lib().gf2e_mul_add_async(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                        e, f, _stream_handle(stream)), "gf2e_mul_add_async")
+        return C
+
+    def mul_add(self, A, B, C, e: int, f: int, stream=None):
+        self.mul_add_async(A, B, C, e, f, stream=stream)
+        self.sync(stream)
+        return C
+
+    # -- triangular solving ---------------------------------------------------
+    def trsm_async(self, T, B, e: int, f: int, lower: bool = False, unit: bool = False, stream=None):
+        """B <- T^{-1} B in place, T triangular (see gf2e_trsm_async)."""
+        _check_elem(T, e, "T")
+        _check_elem(B, e, "B")
+        t, b = mat(T), mat(B)
+        _check(lib().gf2e_trsm_async(self.handle, 1 if lower else 0, 1 if unit else 0, ctypes.byref(t),
+                                     ctypes.byref(b), e, f, _stream_handle(stream)), "gf2e_trsm_async")
+        return B
+
+    def trsm(self, T, B, e: int, f: int, lower: bool = False, unit: bool = False, stream=None):
+        self.trsm_async(T, B, e, f, lower=lower, unit=unit, stream=stream)
+        self.sync(stream)
+        return B
 
     # -- batched -------------------------------------------------------------
     def _batch_args(self, As, Bs, Cs, es, fs):

@@ -272,7 +272,7 @@ void Ctx::save_tune_entry(uint64_t key, int choice)
 }
 
 int Ctx::exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                   int64_t ldc, hipStream_t s)
+                   int64_t ldc, hipStream_t s, bool acc)
 {
     uint64_t* Apl = static_cast<uint64_t*>(ws);
     uint64_t* Bpl = Apl + p.a_bytes / 8;
@@ -299,8 +299,8 @@ int Ctx::exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const vo
         StageTimer t(this, GF2E_STAGE_COMBINE, s);
         // Alpha form: result plane c is the column block c of the one product.
         err = p.form == kFormAlpha
-                  ? launch_combine(p.e, p.sid, p.f, P, p.Np / 64, p.gNp / 64, p.m, p.n, C, ldc, s)
-                  : launch_combine(p.e, p.sid, p.f, P, p.Mp * (p.Np / 64), p.Np / 64, p.m, p.n, C, ldc, s);
+                  ? launch_combine(p.e, p.sid, p.f, P, p.Np / 64, p.gNp / 64, p.m, p.n, C, ldc, s, acc)
+                  : launch_combine(p.e, p.sid, p.f, P, p.Mp * (p.Np / 64), p.Np / 64, p.m, p.n, C, ldc, s, acc);
     }
     return err == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
 }
@@ -402,7 +402,7 @@ int Ctx::tune_now(int e, uint32_t f, int64_t m, int64_t k, int64_t n, hipStream_
     return GF2E_OK;
 }
 
-int Ctx::mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, hipStream_t s)
+int Ctx::mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, hipStream_t s, bool acc)
 {
     const int64_t m = A->rows, k = A->cols, n = B->cols;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -416,7 +416,7 @@ int Ctx::mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* 
     int kind = choose_kind(p);
     if (!kind_supports(kind, p)) kind = GEMM_MFMA_256x256_W8;  // f32 counts would not be exact
     if ((rc = ensure_workspace(p.a_bytes + p.b_bytes + p.p_bytes, s))) return rc;
-    return exec_plan(p, kind, A->data, A->ld, B->data, B->ld, C->data, C->ld, s);
+    return exec_plan(p, kind, A->data, A->ld, B->data, B->ld, C->data, C->ld, s, acc);
 }
 
 }  // namespace gf2e
@@ -441,6 +441,7 @@ const char* gf2e_strerror(int code)
         case GF2E_ENOMEM: return "workspace allocation failed or exceeds the limit";
         case GF2E_EDEVICE: return "HIP runtime error";
         case GF2E_EBUSY: return "request does not fit the memory budget now";
+        case GF2E_ESINGULAR: return "triangular matrix has a zero on its diagonal";
         default: return "unknown error";
     }
 }
@@ -543,6 +544,7 @@ void gf2e_destroy(gf2e_ctx* handle)
     (void)hipDeviceSynchronize();
     c->release_batches();
     if (c->ws) (void)hipFree(c->ws);
+    if (c->aux) (void)hipFree(c->aux);
     if (c->d_err) (void)hipFree(c->d_err);
     for (int st = 0; st < GF2E_NUM_STAGES; ++st)
         for (auto& pr : c->prof_pending[st]) {
@@ -589,7 +591,7 @@ int gf2e_sync(gf2e_ctx* handle, void* stream)
         const int zero = 0;
         if (hipMemcpy(c->d_err, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
             return GF2E_EDEVICE;
-        return GF2E_ERANGE;
+        return (flag & 1) ? GF2E_ERANGE : GF2E_ESINGULAR;
     }
     return GF2E_OK;
 }

@@ -61,4 +61,25 @@ inline uint32_t x_pow_mod(int d, uint32_t f, int e)
     return r;
 }
 
+// Multiplicative order of a nonzero element a.
+inline uint32_t element_order(uint32_t a, uint32_t f, int e)
+{
+    uint32_t x = a, k = 1;
+    while (x != 1u) {
+        x = polymulmod(x, a, f, e);
+        ++k;
+    }
+    return k;
+}
+
+// Smallest generator of the multiplicative group of F_2[x]/<f> (it is cyclic
+// of order 2^e - 1; f need not be primitive).
+inline uint32_t find_generator(int e, uint32_t f)
+{
+    const uint32_t q = (1u << e) - 1u;
+    for (uint32_t g = 2; g <= q; ++g)
+        if (element_order(g, f, e) == q) return g;
+    return 1u;  // F_4 has q = 3 and generator 2; only reached for e < 2
+}
+
 }  // namespace gf2e

@@ -67,10 +67,11 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
 hipError_t launch_slice_cols_alpha(int e, uint32_t f, const void* B, int64_t ldb, int64_t k, int64_t n,
                                    uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s);
 // Recombine the T products into result planes (reducing mod f for Karatsuba
-// schedules) and write C (m x n elements).  Product s, row i, word w is at
-// P[s*pstride + i*ldp + w] (pstride = Mp*ldp for the grouped layout above).
+// schedules) and write C (m x n elements), or add to C when acc is set.
+// Product s, row i, word w is at P[s*pstride + i*ldp + w] (pstride = Mp*ldp
+// for the grouped layout above).
 hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t pstride, int64_t ldp,
-                          int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s);
+                          int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s, bool acc = false);
 // One product of a batch, as the batched kernels read it from device memory.
 struct BatchProduct {
     const void* A;

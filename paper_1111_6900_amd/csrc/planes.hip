@@ -185,11 +185,12 @@ __device__ __attribute__((always_inline)) inline void slice_col_word_alpha(const
 
 // Combine of one word: word w of row i of every product plane becomes 64
 // elements of C.  Product s, row i, word w is at P[s*pstride + i*ldp + w].
-// k0 set: the product has an empty inner dimension, C = 0.
+// k0 set: the product has an empty inner dimension, C = 0.  acc set: the
+// result is added to C (C += A*B) instead of replacing it.
 template <int E, int SID>
 __device__ __attribute__((always_inline)) inline void combine_word(const uint64_t* __restrict__ P, int64_t pstride,
                                     int64_t ldp, int64_t n, uint32_t f, void* __restrict__ C,
-                                    int64_t ldc, int64_t i, int64_t w, bool k0)
+                                    int64_t ldc, int64_t i, int64_t w, bool k0, bool acc = false)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     constexpr KernelSchedule S = kernel_schedule(E, SID);
@@ -262,14 +263,19 @@ __device__ __attribute__((always_inline)) inline void combine_word(const uint64_
                     wd[h] = uint32_t(out[16 * q + 4 * h]) | (uint32_t(out[16 * q + 4 * h + 1]) << 8) |
                             (uint32_t(out[16 * q + 4 * h + 2]) << 16) |
                             (uint32_t(out[16 * q + 4 * h + 3]) << 24);
-                v[q] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                uint4 o = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                if (acc) {
+                    const uint4 old = v[q];
+                    o.x ^= old.x; o.y ^= old.y; o.z ^= old.z; o.w ^= old.w;
+                }
+                v[q] = o;
             }
             return;
         }
     }
 #pragma unroll
     for (int b = 0; b < 64; ++b)
-        if (b < valid) dst[b] = out[b];
+        if (b < valid) dst[b] = acc ? elem_t(dst[b] ^ out[b]) : out[b];
 }
 
 template <int E, int SID>
@@ -305,13 +311,13 @@ __global__ __launch_bounds__(kThreads) void slice_cols_alpha_kernel(
 template <int E, int SID>
 __global__ __launch_bounds__(kThreads) void combine_kernel(
     const uint64_t* __restrict__ P, int64_t pstride, int64_t ldp, int64_t m, int64_t n, uint32_t f,
-    void* __restrict__ C, int64_t ldc)
+    void* __restrict__ C, int64_t ldc, int acc)
 {
     const int64_t nw = (n + 63) / 64;
     const int64_t w = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (w >= nw) return;
     for (int64_t i = blockIdx.y; i < m; i += gridDim.y)
-        combine_word<E, SID>(P, pstride, ldp, n, f, C, ldc, i, w, false);
+        combine_word<E, SID>(P, pstride, ldp, n, f, C, ldc, i, w, false, acc != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,13 +492,13 @@ hipError_t launch_slice_cols_alpha(int e, uint32_t f, const void* B, int64_t ldb
 }
 
 hipError_t launch_combine(int e, int sid, uint32_t f, const uint64_t* P, int64_t pstride, int64_t ldp,
-                          int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s)
+                          int64_t m, int64_t n, void* C, int64_t ldc, hipStream_t s, bool acc)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
     dim3 grid(unsigned(ceil_div(ceil_div(n, 64), kThreads)), unsigned(m < 65535 ? m : 65535));
     if (!with_any_schedule(e, sid, [&]<int E, int SID>() {
             hipLaunchKernelGGL((combine_kernel<E, SID>), grid, dim3(kThreads), 0, s, P, pstride, ldp, m, n, f,
-                               C, ldc);
+                               C, ldc, acc ? 1 : 0);
         }))
         return hipErrorInvalidValue;
     return hipGetLastError();

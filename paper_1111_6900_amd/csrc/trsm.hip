@@ -1,0 +1,309 @@
+// Triangular solving with matrices over F_{2^e} (M4RIE paper, Section 4.3):
+// X = T^{-1} B for a triangular m x m matrix T, B overwritten by X.
+//
+// The paper's algorithm walks the rows one by one and updates the rows above
+// with Newton-John tables.  Here the solve is blocked for the GPU:
+//   1. one kernel inverts all 128 x 128 diagonal blocks of T at once (one
+//      workgroup per block, one thread per column of the inverse, field
+//      products by log/antilog tables in LDS);
+//   2. a recursion over block ranges turns the rest into products on the
+//      bitsliced path: for upper T,
+//          X2 = solve(T22, B2);  B1 += T12 * X2;  X1 = solve(T11, B1),
+//      and a single block row is X_q = inv(T_qq) * B_q.
+// Every update is a gf2e product (C += A*B), so almost all of the work runs
+// on the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "ctx.hpp"
+#include "field.hpp"
+#include "gf2e.h"
+#include "gf2e_internal.hpp"
+
+namespace gf2e {
+
+namespace {
+
+constexpr int kTrsmBlock = 128;  // diagonal block size = threads per workgroup
+
+__device__ inline uint32_t polymul_dev(uint32_t a, uint32_t b, uint32_t f, int e)
+{
+    uint32_t r = 0;
+    while (b) {
+        if (b & 1u) r ^= a;
+        b >>= 1;
+        a <<= 1;
+        if ((a >> e) & 1u) a ^= f;
+    }
+    return r;
+}
+
+// Log/antilog tables of F_{2^E}: exp[i] = g^i for i < 2q (q = 2^E - 1), log
+// the inverse map on nonzero elements.
+template <int E>
+struct FieldTabs {
+    static constexpr int Q = (1 << E) - 1;
+    uint16_t exp[2 * Q];
+    uint16_t log[Q + 1];
+
+    __device__ uint32_t mul(uint32_t a, uint32_t b) const { return (a && b) ? exp[log[a] + log[b]] : 0u; }
+    __device__ uint32_t inv(uint32_t a) const { return exp[Q - log[a]]; }  // a != 0
+};
+
+// Every thread fills a run of consecutive powers, starting from g^start by
+// square and multiply.
+template <int E>
+__device__ void build_tabs(FieldTabs<E>& T, uint32_t f, uint32_t g)
+{
+    constexpr int Q = FieldTabs<E>::Q;
+    const int per = (Q + int(blockDim.x) - 1) / int(blockDim.x);
+    const int i0 = int(threadIdx.x) * per;
+    if (i0 < Q) {
+        uint32_t x = 1, base = g;
+        for (int b = i0; b; b >>= 1) {
+            if (b & 1) x = polymul_dev(x, base, f, E);
+            base = polymul_dev(base, base, f, E);
+        }
+        const int i1 = i0 + per < Q ? i0 + per : Q;
+        for (int i = i0; i < i1; ++i) {
+            T.exp[i] = uint16_t(x);
+            T.exp[i + Q] = uint16_t(x);
+            T.log[x] = uint16_t(i);
+            x = polymul_dev(x, g, f, E);
+        }
+    }
+    if (threadIdx.x == 0) T.log[0] = 0;  // never used: mul tests for zero
+    __syncthreads();
+}
+
+// Inverse of diagonal block q of T (rows and columns [128q, 128q + bs)),
+// written row-major with leading dimension 128 at Tinv + 128q*128.  Thread c
+// computes column c of the inverse by substitution on T_qq x = e_c.  Only
+// the triangle of T is read; unit = 1 takes the diagonal as ones.  Flags:
+// err |= 1 for an entry >= 2^E, err |= 2 for a zero on the diagonal.
+template <int E>
+__global__ __launch_bounds__(kTrsmBlock) void trsm_invert_kernel(const void* __restrict__ Tm, int64_t ldt,
+                                                                 int64_t m, int lower, int unit, uint32_t f,
+                                                                 uint32_t g, void* __restrict__ Tinv,
+                                                                 int* __restrict__ err)
+{
+    using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
+    __shared__ FieldTabs<E> tabs;
+    __shared__ uint16_t Ts[kTrsmBlock][kTrsmBlock + 1];
+    __shared__ uint16_t Xs[kTrsmBlock][kTrsmBlock + 1];
+    build_tabs<E>(tabs, f, g);
+
+    const int64_t r0 = int64_t(blockIdx.x) * kTrsmBlock;
+    const int bs = int(m - r0 < kTrsmBlock ? m - r0 : kTrsmBlock);
+    const elem_t* T = static_cast<const elem_t*>(Tm);
+    const int c = threadIdx.x;
+    bool bad = false;
+    for (int i = 0; i < bs; ++i) {
+        uint32_t v = 0;
+        const bool inside = c < bs && (lower ? c <= i : c >= i);
+        if (inside && !(unit && c == i)) {
+            v = T[(r0 + i) * ldt + r0 + c];
+            bad |= (v >> E) != 0;
+            v &= (1u << E) - 1u;
+        }
+        Ts[i][c] = uint16_t(v);
+    }
+    __syncthreads();
+    if (bad) atomicOr(err, 1);
+    if (!unit && c < bs && Ts[c][c] == 0) atomicOr(err, 2);
+
+    if (c < bs) {
+        for (int step = 0; step < bs; ++step) {
+            const int i = lower ? step : bs - 1 - step;
+            uint32_t x = 0;
+            if (lower ? i >= c : i <= c) {
+                uint32_t acc = i == c ? 1u : 0u;
+                if (lower) {
+                    for (int l = c; l < i; ++l) acc ^= tabs.mul(Ts[i][l], Xs[l][c]);
+                } else {
+                    for (int l = i + 1; l <= c; ++l) acc ^= tabs.mul(Ts[i][l], Xs[l][c]);
+                }
+                const uint32_t d = Ts[i][i];
+                x = unit ? acc : (d ? tabs.mul(tabs.inv(d), acc) : 0u);
+            }
+            Xs[i][c] = uint16_t(x);
+        }
+    }
+    __syncthreads();
+    elem_t* out = static_cast<elem_t*>(Tinv);
+    if (c < bs)
+        for (int i = 0; i < bs; ++i) out[(r0 + i) * kTrsmBlock + c] = elem_t(Xs[i][c]);
+}
+
+template <class Fn>
+bool with_e_host(int e, Fn&& fn)
+{
+    switch (e) {
+        case 2: fn.template operator()<2>(); return true;
+        case 3: fn.template operator()<3>(); return true;
+        case 4: fn.template operator()<4>(); return true;
+        case 5: fn.template operator()<5>(); return true;
+        case 6: fn.template operator()<6>(); return true;
+        case 7: fn.template operator()<7>(); return true;
+        case 8: fn.template operator()<8>(); return true;
+        case 9: fn.template operator()<9>(); return true;
+        case 10: fn.template operator()<10>(); return true;
+        default: return false;
+    }
+}
+
+hipError_t launch_trsm_invert(int e, uint32_t f, int lower, int unit, const void* T, int64_t ldt, int64_t m,
+                              void* Tinv, int* err, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    const uint32_t g = find_generator(e, f);
+    const dim3 grid(unsigned(ceil_div(m, kTrsmBlock)));
+    if (!with_e_host(e, [&]<int E>() {
+            hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kTrsmBlock), 0, s, T, ldt, m, lower, unit, f, g,
+                               Tinv, err);
+        }))
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+gf2e_mat sub(const gf2e_mat* M, int esz, int64_t r, int64_t c, int64_t rows, int64_t cols)
+{
+    gf2e_mat s;
+    s.data = static_cast<uint8_t*>(M->data) + (r * M->ld + c) * esz;
+    s.rows = rows;
+    s.cols = cols;
+    s.ld = M->ld;
+    return s;
+}
+
+}  // namespace
+
+int Ctx::ensure_aux(int64_t bytes, hipStream_t s)
+{
+    if (bytes <= aux_bytes) return GF2E_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cs);
+    if (cs != hipStreamCaptureStatusNone) return GF2E_ENOMEM;
+    if (aux) {
+        if (hipDeviceSynchronize() != hipSuccess) return GF2E_EDEVICE;
+        (void)hipFree(aux);
+        aux = nullptr;
+        aux_bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, size_t(bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return GF2E_ENOMEM;
+    }
+    aux = p;
+    aux_bytes = bytes;
+    return GF2E_OK;
+}
+
+int Ctx::trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f, hipStream_t s)
+{
+    const int64_t m = T->rows, n = B->cols;
+    if (m == 0 || n == 0) return GF2E_OK;
+    const int esz = elem_bytes(e);
+    const int64_t nb = ceil_div(m, kTrsmBlock);
+    const int64_t inv_bytes = round_up(nb * kTrsmBlock * kTrsmBlock * esz, 256);
+    const int64_t tmp_bytes = round_up(int64_t(kTrsmBlock) * n * esz, 256);
+    int rc = ensure_aux(inv_bytes + tmp_bytes, s);
+    if (rc) return rc;
+    uint8_t* Tinv = static_cast<uint8_t*>(aux);
+    uint8_t* tmp = Tinv + inv_bytes;
+    if (launch_trsm_invert(e, f, lower, unit, T->data, T->ld, m, Tinv, d_err, s) != hipSuccess) return GF2E_EDEVICE;
+
+    const gf2e_mat inv_all{Tinv, nb * kTrsmBlock, kTrsmBlock, kTrsmBlock};
+    // Solve block rows [q0, q1).
+    auto solve = [&](auto&& self, int64_t q0, int64_t q1) -> int {
+        const int64_t R0 = q0 * kTrsmBlock, R1 = std::min(m, q1 * kTrsmBlock);
+        if (q1 - q0 == 1) {
+            const int64_t bs = R1 - R0;
+            const gf2e_mat Ti = sub(&inv_all, esz, R0, 0, bs, bs);
+            const gf2e_mat Bq = sub(B, esz, R0, 0, bs, n);
+            gf2e_mat Xq{tmp, bs, n, n};
+            int r = mul(e, f, &Ti, &Bq, &Xq, s);
+            if (r) return r;
+            if (hipMemcpy2DAsync(Bq.data, size_t(B->ld * esz), tmp, size_t(n * esz), size_t(n * esz), size_t(bs),
+                                 hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return GF2E_EDEVICE;
+            return GF2E_OK;
+        }
+        const int64_t mid = (q0 + q1) / 2, Rm = mid * kTrsmBlock;
+        int r;
+        if (!lower) {
+            if ((r = self(self, mid, q1))) return r;
+            const gf2e_mat A = sub(T, esz, R0, Rm, Rm - R0, R1 - Rm);
+            const gf2e_mat X2 = sub(B, esz, Rm, 0, R1 - Rm, n);
+            gf2e_mat B1 = sub(B, esz, R0, 0, Rm - R0, n);
+            if ((r = mul(e, f, &A, &X2, &B1, s, true))) return r;
+            return self(self, q0, mid);
+        }
+        if ((r = self(self, q0, mid))) return r;
+        const gf2e_mat A = sub(T, esz, Rm, R0, R1 - Rm, Rm - R0);
+        const gf2e_mat X1 = sub(B, esz, R0, 0, Rm - R0, n);
+        gf2e_mat B2 = sub(B, esz, Rm, 0, R1 - Rm, n);
+        if ((r = mul(e, f, &A, &X1, &B2, s, true))) return r;
+        return self(self, mid, q1);
+    };
+    return solve(solve, 0, nb);
+}
+
+}  // namespace gf2e
+
+using namespace gf2e;
+
+extern "C" {
+
+int gf2e_mul_add_async(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e, uint32_t f,
+                       void* stream)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c) return GF2E_EINVAL;
+    int rc = validate_mul(A, B, C, e, f);
+    if (rc) return rc;
+    if (A->rows == 0 || B->cols == 0 || A->cols == 0) return GF2E_OK;  // C += 0
+    DeviceGuard guard(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    c->order_stream(s);
+    rc = c->mul(e, f, A, B, C, s, true);
+    c->mark_used(s);
+    return rc;
+}
+
+int gf2e_mul_add(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e, uint32_t f)
+{
+    int rc = gf2e_mul_add_async(handle, A, B, C, e, f, nullptr);
+    if (rc) return rc;
+    return gf2e_sync(handle, nullptr);
+}
+
+int gf2e_trsm_async(gf2e_ctx* handle, int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f,
+                    void* stream)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c) return GF2E_EINVAL;
+    int rc;
+    if ((rc = check_mat(T)) || (rc = check_mat(B))) return rc;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
+    if (T->rows != T->cols || B->rows != T->rows) return GF2E_ESHAPE;
+    if (overlaps(B, T, elem_bytes(e))) return GF2E_EALIAS;
+    DeviceGuard guard(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    c->order_stream(s);
+    rc = c->trsm(lower != 0, unit != 0, T, B, e, f, s);
+    c->mark_used(s);
+    return rc;
+}
+
+int gf2e_trsm(gf2e_ctx* handle, int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f)
+{
+    int rc = gf2e_trsm_async(handle, lower, unit, T, B, e, f, nullptr);
+    if (rc) return rc;
+    return gf2e_sync(handle, nullptr);
+}
+
+}  // extern "C"

@@ -46,7 +46,8 @@ def test_binding_covers_the_header():
 
 def test_strerror_for_every_code():
     g = _gf2e()
-    codes = [g.OK, g.EINVAL, g.EFIELD, g.ESHAPE, g.EALIAS, g.ERANGE, g.ENOMEM, g.EDEVICE, g.EBUSY]
+    codes = [g.OK, g.EINVAL, g.EFIELD, g.ESHAPE, g.EALIAS, g.ERANGE, g.ENOMEM, g.EDEVICE, g.EBUSY,
+             g.ESINGULAR]
     msgs = [g.strerror(c) for c in codes]
     assert len(set(msgs)) == len(msgs)
     assert g.strerror(-1234) == "unknown error"
