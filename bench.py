@@ -67,6 +67,7 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-trsm", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
@@ -81,7 +82,7 @@ def log(args, *msg):
         print("[bench]", *msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, B, e, f, budget_s):
+def cpu_baseline(A, B, e, f, budget_s, trsm_workload=None):
     """The oracle on whole rows of the same product until the budget is used."""
     import oracle
     threads = oracle.max_threads()
@@ -96,9 +97,20 @@ def cpu_baseline(A, B, e, f, budget_s):
         if dt < budget_s / 8:
             chunk *= 2
     macs = rows * k * n
-    return {"value": macs / spent, "unit": "element-MAC/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows} of {A.shape[0]} rows of C ({rows}x{k}x{n} element-MAC), "
-                      f"{spent:.1f} s on {threads} threads"}
+    out = {"value": macs / spent, "unit": "element-MAC/s", "cores": threads, "kind": "oracle",
+           "sample": f"{rows} of {A.shape[0]} rows of C ({rows}x{k}x{n} element-MAC), "
+                     f"{spent:.1f} s on {threads} threads"}
+    if trsm_workload is not None:
+        # The oracle's triangular solve (Section 4.3 row algorithm) on a
+        # column sample of the TRSM leg's smallest system.
+        m, cols = TRSM_SIZES[0], min(64 * threads, TRSM_SIZES[0])  # 64-column chunks per thread
+        U, Bt = trsm_system(trsm_workload, m, TRSM_E)
+        t0 = time.perf_counter()
+        oracle.trsm(U, Bt[:, :cols], TRSM_E, TRSM_F, nthreads=threads)
+        dt = time.perf_counter() - t0
+        out["trsm"] = {"value": m * m * cols / 2 / dt, "unit": "element-MAC/s",
+                       "sample": f"{cols} of {m} columns of the {m}x{m} solve, {dt:.2f} s on {threads} threads"}
+    return out
 
 
 def batched_leg(g, torch, workload, log, reps=5):
@@ -178,6 +190,52 @@ def forms_leg(g, torch, workload, log, reps=10):
         res[name] = row
         ctx.close()
         del Ad, Bd, C
+    return res
+
+
+def trsm_system(workload, m, e):
+    """The seeded upper triangular system of the TRSM leg: U (m x m, nonzero
+    diagonal) and B (m x m) over F_2^e."""
+    import numpy as np
+    gen = np.random.default_rng(70000 + m)
+    U = np.triu(workload.field_matrix(gen, m, m, e))
+    np.fill_diagonal(U, gen.integers(1, 1 << e, m))
+    B = workload.field_matrix(gen, m, m, e)
+    return U, B
+
+
+TRSM_SIZES, TRSM_E, TRSM_F = (4096, 8192), 8, 0x11D
+
+
+def trsm_leg(g, torch, workload, log, reps=5):
+    """Triangular solves X = U^{-1} B (U upper, m x m; B m x m) over F_256:
+    time per solve and element-MAC/s counting m*m*n/2 multiply-adds."""
+    import numpy as np
+    res = {}
+    e, f = TRSM_E, TRSM_F
+    ctx = g.Context(0, autotune=True)
+    for m in TRSM_SIZES:
+        U, B = trsm_system(workload, m, e)
+        Ud = torch.from_numpy(U).to(g.elem_dtype(e)).cuda()
+        B0 = torch.from_numpy(B).to(g.elem_dtype(e)).cuda()
+        X = B0.clone()
+        ctx.trsm(Ud, X, e, f)  # tunes the product sizes it meets
+        times = []
+        for _ in range(reps):
+            X.copy_(B0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.trsm_async(Ud, X, e, f)
+            e1.record()
+            ctx.sync()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        row = {"m": m, "n": m, "e": e, "ms": round(ms, 3), "element_mac_per_s": m * m * m / 2 / (ms / 1e3)}
+        log(f"trsm {row}")
+        res[f"{m}"] = row
+        del Ud, B0, X
+    ctx.close()
     return res
 
 
@@ -271,7 +329,7 @@ def main():
     C = torch.empty((m, n), dtype=g.elem_dtype(e), device="cuda")
 
     if args.profile_run:
-        args.no_cpu = args.no_batched = args.no_serve = args.no_forms = True
+        args.no_cpu = args.no_batched = args.no_serve = args.no_forms = args.no_trsm = True
         # A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
         # counters calibrate the byte counts read for the product kernels.
         src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -374,6 +432,8 @@ def main():
 
     if not args.no_forms:
         out["forms"] = forms_leg(g, torch, workload, lambda *a: log(args, *a))
+    if not args.no_trsm:
+        out["trsm"] = trsm_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_batched:
         out["batched"] = batched_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_serve:
@@ -381,7 +441,8 @@ def main():
 
     if not args.no_cpu:
         log(args, "timing the CPU oracle on a row sample")
-        out["cpu_baseline"] = cpu_baseline(A, B, e, f, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A, B, e, f, args.cpu_seconds,
+                                           None if args.no_trsm else workload)
 
     print(json.dumps(out), flush=True)
 
