@@ -66,6 +66,7 @@ def _load():
     lib.gf2e_oracle_freivalds.restype = i64
     lib.gf2e_oracle_max_threads.restype = i32
     lib.gf2e_oracle_trsm.argtypes = [i32, u32, i32, i32, i64, i64, vp, i64, vp, i64, i32]
+    lib.gf2e_oracle_echelon.argtypes = [i32, u32, i32, i64, i64, vp, i64, vp, vp]
     _lib = lib
     return lib
 
@@ -193,6 +194,20 @@ def trsm(T, B, e: int, f: int, lower: bool = False, unit: bool = False, nthreads
     _check(_load().gf2e_oracle_trsm(e, f, 1 if lower else 0, 1 if unit else 0, m, n, _ptr(T), m,
                                     _ptr(X), n, nthreads))
     return X
+
+
+def echelon(A, e: int, f: int, full: bool = True):
+    """(E, rank, pivots): the row echelon form of A by the elimination loop of
+    Section 4.1 (reduced when full), its rank and the pivot column of each of
+    its first rank rows.  A is not modified."""
+    E = _as_field_matrix(A, e).copy()
+    m, n = E.shape
+    rank = ctypes.c_int64(0)
+    piv = np.zeros(max(min(m, n), 1), dtype=np.int64)
+    _check(_load().gf2e_oracle_echelon(e, f, 1 if full else 0, m, n, _ptr(E), n, ctypes.byref(rank),
+                                       _ptr(piv)))
+    r = int(rank.value)
+    return E, r, piv[:r].copy()
 
 
 def max_threads() -> int:

@@ -378,3 +378,56 @@ int gf2e_oracle_trsm(int e, uint32_t f, int lower, int unit, int64_t m, int64_t 
     free(T);
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Echelon forms (Section 4.1 elimination, Section 6).                     */
+/* ---------------------------------------------------------------------- */
+
+/* Row echelon form of A (m x n) in place, by the elimination loop of
+ * Section 4.1: for each column j in turn, the first row i >= r with a
+ * nonzero entry there is scaled so the entry becomes 1 and swapped into row
+ * r, and its multiples are added to the rows below it (full = 0) or to every
+ * other row (full = 1, the reduced form); r grows by one.  Returns the rank
+ * in *rank and the pivot column of row t in pivots[t] (t < rank; pivots may
+ * be NULL).  ORC_ERANGE if an entry is not below 2^e (A unchanged). */
+int gf2e_oracle_echelon(int e, uint32_t f, int full, int64_t m, int64_t n, void* A, int64_t lda,
+                        int64_t* rank, int64_t* pivots)
+{
+    if (m < 0 || n < 0 || !rank) return ORC_EINVAL;
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc != ORC_OK) { free(T); return rc; }
+    const int wide = e > 8;
+    if (!all_in_field(A, wide, m, n, lda, 1u << e)) { free(T); return ORC_ERANGE; }
+    int64_t r = 0;
+    for (int64_t j = 0; j < n && r < m; ++j) {
+        int64_t i = r;
+        while (i < m && get_el(A, wide, i * lda + j) == 0) ++i;
+        if (i == m) continue;
+        /* scale row i so that its entry in column j is 1 */
+        const uint32_t d = get_el(A, wide, i * lda + j);
+        const uint32_t dinv = T->exp[T->q - T->log[d]];
+        for (int64_t c = j; c < n; ++c) put_el(A, wide, i * lda + c, tab_mul(T, dinv, get_el(A, wide, i * lda + c)));
+        /* swap rows i and r */
+        if (i != r)
+            for (int64_t c = 0; c < n; ++c) {
+                const uint32_t a = get_el(A, wide, i * lda + c), b = get_el(A, wide, r * lda + c);
+                put_el(A, wide, i * lda + c, b);
+                put_el(A, wide, r * lda + c, a);
+            }
+        /* add multiples of row r to the other rows */
+        for (int64_t k = full ? 0 : r + 1; k < m; ++k) {
+            if (k == r) continue;
+            const uint32_t x = get_el(A, wide, k * lda + j);
+            if (!x) continue;
+            for (int64_t c = j; c < n; ++c)
+                put_el(A, wide, k * lda + c, get_el(A, wide, k * lda + c) ^ tab_mul(T, x, get_el(A, wide, r * lda + c)));
+        }
+        if (pivots) pivots[r] = j;
+        ++r;
+    }
+    *rank = r;
+    free(T);
+    return ORC_OK;
+}
