@@ -204,6 +204,18 @@ int gf2e_trsm_async(gf2e_ctx* ctx, int lower, int unit, const gf2e_mat* T, gf2e_
                     uint32_t f, void* stream);
 int gf2e_trsm(gf2e_ctx* ctx, int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f);
 
+/* Row echelon form of A (m x n) in place (Sections 4.1 and 6): with full = 1
+ * the reduced row echelon form (unique: every pivot is 1 and the only
+ * nonzero of its column), with full = 0 a row echelon form whose pivots are
+ * 1 with zeros below them.  *rank receives the rank; pivots (may be NULL,
+ * else room for min(m, n) entries) receives the pivot column of rows
+ * 0..rank-1.  Blocking (the null stream; the host reads each panel's pivot
+ * count).  GF2E_ERANGE if an entry is >= 2^e (A is then unchanged).  The
+ * context's buffers hold two copies of a 64-column panel and room for the
+ * rows below the current rank (about m*n elements). */
+int gf2e_echelonize(gf2e_ctx* ctx, gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank,
+                    int64_t* pivots);
+
 const char* gf2e_strerror(int code);
 
 /* ---- Field and schedule queries (host only; need no GPU) ---------------- */

@@ -86,6 +86,7 @@ _SIGS = {
     "gf2e_mul_add": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
     "gf2e_trsm_async": (_i32, [_vp, _i32, _i32, _P(Mat), _P(Mat), _i32, _u32, _vp]),
     "gf2e_trsm": (_i32, [_vp, _i32, _i32, _P(Mat), _P(Mat), _i32, _u32]),
+    "gf2e_echelonize": (_i32, [_vp, _P(Mat), _i32, _u32, _i32, _P(_i64), _vp]),
     "gf2e_mul_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_set_batch_threshold": (_i32, [_vp, _i64]),
     "gf2e_tune_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -297,6 +298,19 @@ class Context:
         self.trsm_async(T, B, e, f, lower=lower, unit=unit, stream=stream)
         self.sync(stream)
         return B
+
+    # -- echelon forms ----------------------------------------------------------
+    def echelonize(self, A, e: int, f: int, full: bool = True):
+        """Row echelon form of A in place (reduced when full); returns
+        (rank, pivot columns as a list)."""
+        _check_elem(A, e, "A")
+        a = mat(A)
+        rank = ctypes.c_int64(0)
+        piv = (ctypes.c_int64 * max(1, min(A.size(0), A.size(1))))()
+        _check(lib().gf2e_echelonize(self.handle, ctypes.byref(a), e, f, 1 if full else 0, ctypes.byref(rank),
+                                     ctypes.cast(piv, ctypes.c_void_p)), "gf2e_echelonize")
+        r = int(rank.value)
+        return r, [int(piv[t]) for t in range(r)]
 
     # -- batched -------------------------------------------------------------
     def _batch_args(self, As, Bs, Cs, es, fs):

@@ -113,6 +113,13 @@ struct Ctx {
     int64_t aux_bytes = 0;
     int ensure_aux(int64_t bytes, hipStream_t s);
     int trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f, hipStream_t s);
+
+    // Log/antilog tables of F_2[x]/<f> in device memory (exp[2q] then
+    // log[q+1], uint16), built on first use and kept per (e, f).
+    std::map<uint64_t, uint16_t*> ftabs;
+    const uint16_t* field_tables(int e, uint32_t f);
+    // Row echelon form in place (reduced when full); host-synchronous.
+    int echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s);
     void release_batches();
 };
 
