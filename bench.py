@@ -68,6 +68,7 @@ def parse_args():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-trsm", action="store_true")
+    ap.add_argument("--no-echelon", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
@@ -82,7 +83,7 @@ def log(args, *msg):
         print("[bench]", *msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, B, e, f, budget_s, trsm_workload=None):
+def cpu_baseline(A, B, e, f, budget_s, workload_mod=None, echelon=False, no_trsm=False):
     """The oracle on whole rows of the same product until the budget is used."""
     import oracle
     threads = oracle.max_threads()
@@ -100,16 +101,27 @@ def cpu_baseline(A, B, e, f, budget_s, trsm_workload=None):
     out = {"value": macs / spent, "unit": "element-MAC/s", "cores": threads, "kind": "oracle",
            "sample": f"{rows} of {A.shape[0]} rows of C ({rows}x{k}x{n} element-MAC), "
                      f"{spent:.1f} s on {threads} threads"}
-    if trsm_workload is not None:
+    if workload_mod is not None and not no_trsm:
         # The oracle's triangular solve (Section 4.3 row algorithm) on a
         # column sample of the TRSM leg's smallest system.
         m, cols = TRSM_SIZES[0], min(64 * threads, TRSM_SIZES[0])  # 64-column chunks per thread
-        U, Bt = trsm_system(trsm_workload, m, TRSM_E)
+        U, Bt = trsm_system(workload_mod, m, TRSM_E)
         t0 = time.perf_counter()
         oracle.trsm(U, Bt[:, :cols], TRSM_E, TRSM_F, nthreads=threads)
         dt = time.perf_counter() - t0
         out["trsm"] = {"value": m * m * cols / 2 / dt, "unit": "element-MAC/s",
                        "sample": f"{cols} of {m} columns of the {m}x{m} solve, {dt:.2f} s on {threads} threads"}
+    if echelon:
+        # The oracle's elimination loop (single-threaded) on a 2048^2 matrix
+        # over F_256 drawn like the echelon leg's.
+        import numpy as np
+        m, e8, f8 = 2048, 8, 0x11D
+        A8 = workload_mod.field_matrix(np.random.default_rng(90000 + m + e8), m, m, e8)
+        t0 = time.perf_counter()
+        _, r8, _ = oracle.echelon(A8, e8, f8)
+        dt = time.perf_counter() - t0
+        out["echelon"] = {"value": m * m * r8 / dt, "unit": "element-MAC/s",
+                          "sample": f"RREF of a {m}x{m} matrix over F_256 (rank {r8}), {dt:.2f} s on 1 thread"}
     return out
 
 
@@ -239,6 +251,38 @@ def trsm_leg(g, torch, workload, log, reps=5):
     return res
 
 
+ECHELON_CASES = ((4096, 2, 0x7), (4096, 8, 0x11D), (8192, 2, 0x7), (8192, 8, 0x11D))
+
+
+def echelon_leg(g, torch, workload, log, reps=3):
+    """Reduced row echelon forms of random square matrices (full rank with
+    high probability): ms per form and element-MAC/s counting m*n*rank
+    multiply-adds (the cost of the elimination loop of Section 4.1)."""
+    import numpy as np
+    res = {}
+    ctx = g.Context(0, autotune=True)
+    for m, e, f in ECHELON_CASES:
+        A = workload.field_matrix(np.random.default_rng(90000 + m + e), m, m, e)
+        A0 = torch.from_numpy(A).to(g.elem_dtype(e)).cuda()
+        Ad = A0.clone()
+        r, _ = ctx.echelonize(Ad, e, f)  # tunes the product sizes it meets
+        times = []
+        for _ in range(reps):
+            Ad.copy_(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r, _ = ctx.echelonize(Ad, e, f)
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = float(np.median(times))
+        row = {"m": m, "n": m, "e": e, "rank": r, "ms": round(ms, 2),
+               "element_mac_per_s": m * m * r / (ms / 1e3)}
+        log(f"echelon {row}")
+        res[f"{m}_e{e}"] = row
+        del A0, Ad
+    ctx.close()
+    return res
+
+
 def serve_leg(g, torch, workload, log, count=10000, budget=4 << 30, max_inflight=64, load=0.7):
     """Served requests: n log-uniform in [64, 4096], e ~ U{2..10}.  A closed-loop
     run (all requests at t=0) gives the saturated rate; an open-loop Poisson
@@ -329,7 +373,7 @@ def main():
     C = torch.empty((m, n), dtype=g.elem_dtype(e), device="cuda")
 
     if args.profile_run:
-        args.no_cpu = args.no_batched = args.no_serve = args.no_forms = args.no_trsm = True
+        args.no_cpu = args.no_batched = args.no_serve = args.no_forms = args.no_trsm = args.no_echelon = True
         # A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
         # counters calibrate the byte counts read for the product kernels.
         src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -434,6 +478,8 @@ def main():
         out["forms"] = forms_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_trsm:
         out["trsm"] = trsm_leg(g, torch, workload, lambda *a: log(args, *a))
+    if not args.no_echelon:
+        out["echelon"] = echelon_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_batched:
         out["batched"] = batched_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_serve:
@@ -441,8 +487,8 @@ def main():
 
     if not args.no_cpu:
         log(args, "timing the CPU oracle on a row sample")
-        out["cpu_baseline"] = cpu_baseline(A, B, e, f, args.cpu_seconds,
-                                           None if args.no_trsm else workload)
+        out["cpu_baseline"] = cpu_baseline(A, B, e, f, args.cpu_seconds, workload,
+                                           echelon=not args.no_echelon, no_trsm=args.no_trsm)
 
     print(json.dumps(out), flush=True)
 
