@@ -6,11 +6,11 @@
 // speed, recurses through PLE decomposition so that most of the work becomes
 // matrix products.  Here the matrix is processed in column panels of 64, and
 // per panel:
-//   1. pivots: the panel (rows r..m-1) is copied and eliminated column by
-//      column, one small kernel per column over all rows; each launch picks
-//      the pivot of its column (the first unused row with a nonzero there,
-//      found by atomicMin in the previous launch) and eliminates it from the
-//      other unused rows of the copy.  rp pivots result.
+//   1. pivots: a tournament over the rows r..m-1 of the panel.  Workgroups
+//      of 1024 rows eliminate their rows column by column in LDS and keep
+//      the rows that became pivots; the kept rows of all workgroups go
+//      through the same step again until one workgroup remains, whose pivots
+//      (rp of them, with their columns) are the panel's.
 //   2. W = K^{-1}, where K holds the original entries of the pivot rows at
 //      the pivot columns (one workgroup, Gauss-Jordan in LDS).
 //   3. the pivot rows are moved to rows r..r+rp-1, and on columns c0..n-1:
@@ -38,7 +38,6 @@ namespace gf2e {
 namespace {
 
 constexpr int kPanel = 64;  // columns per panel (max pivots per panel)
-constexpr int kStepThreads = 256;
 
 struct DevField {
     const uint16_t* exp;  // exp[i] = g^i for i < 2q
@@ -73,18 +72,16 @@ __global__ void range_check_kernel(const void* A, int64_t lda, int64_t m, int64_
     if (bad) atomicOr(err, 1);
 }
 
-// Panel copies: orig[i][c] = work[i][c] = A[i][c0 + c] for i < m, c < bc
-// (uint16 entries, row pitch kPanel).
+// Panel copy: orig[i][c] = A[i][c0 + c] (uint16, row pitch kPanel, zero
+// past the panel's last column).
 __global__ void panel_copy_kernel(const void* A, int64_t lda, int64_t m, int64_t c0, int bc, int wide,
-                                  uint16_t* orig, uint16_t* work)
+                                  uint16_t* orig)
 {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= m * kPanel) return;
     const int64_t i = idx / kPanel;
     const int c = int(idx % kPanel);
-    const uint16_t v = c < bc ? uint16_t(ld_el(A, wide, i * lda + c0 + c)) : 0;
-    orig[idx] = v;
-    work[idx] = v;
+    orig[idx] = c < bc ? uint16_t(ld_el(A, wide, i * lda + c0 + c)) : 0;
 }
 
 // State of the pivot search of one panel.
@@ -95,100 +92,165 @@ struct PanelState {
     int rp;                // pivots found
 };
 
-__global__ void panel_reset_kernel(PanelState* st)
-{
-    for (int j = threadIdx.x; j <= kPanel; j += blockDim.x) st->next[j] = INT_MAX;
-    if (threadIdx.x == 0) st->rp = 0;
-}
+// Pivot search by tournament: each workgroup takes up to kSelRows candidate
+// rows of the panel (original entries, from orig), eliminates them column by
+// column in LDS and keeps the rows that became pivots (at most kPanel, in
+// pivot-column order).  Any maximal independent subset of the panel's rows
+// spans its row space, so the rows kept by all workgroups span it too, and a
+// further level over the kept rows (until one workgroup remains) yields a
+// valid pivot set with the panel's pivot columns.  Candidates are row
+// indices relative to r (in == nullptr: rows 0..ncand-1; -1: an empty slot).
+// A workgroup writes its kept rows to out[blockIdx.x*kPanel + t] (-1 past
+// its count); the last level (final) writes the panel state instead.  The
+// kernel is bound by LDS traffic (each step rewrites the remaining columns
+// of every unused row).
+constexpr int kSelRows = 1024;
+constexpr int kSelPitch = kPanel + 2;  // halfwords per LDS row: 33 words, distinct banks
 
-// Rows r..m-1 of the work copy: clear the used flags and offer the rows with
-// a nonzero in column 0 as its pivot.
-__global__ void panel_start_kernel(const uint16_t* work, int64_t r, int64_t m, uint8_t* used, PanelState* st)
+__global__ __launch_bounds__(kSelRows) void panel_select_kernel(const uint16_t* orig, int64_t r, int bc,
+                                                               const int* in, int64_t ncand, int* out, int final,
+                                                               PanelState* st, DevField F)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r + i >= m) return;
-    used[i] = 0;
-    if (work[(r + i) * kPanel] != 0) atomicMin(&st->next[0], int(i));
-}
-
-// Column j of the panel: take its candidate pivot row p (if any), eliminate
-// column j from every other unused row of the work copy, and offer the rows
-// with a nonzero in column j + 1 as that column's pivot.
-__global__ void panel_step_kernel(uint16_t* work, int64_t r, int64_t m, int j, int bc, uint8_t* used,
-                                  PanelState* st, DevField F)
-{
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r + i >= m) return;
-    const int p = st->next[j];
-    uint16_t* row = work + (r + i) * kPanel;
-    if (p != INT_MAX && i == p) {
-        used[i] = 1;
-        const int t = st->rp;  // only this thread writes the pivot list in this launch
-        st->rows[t] = p;
-        st->cols[t] = j;
-        st->rp = t + 1;
-        return;
-    }
-    if (used[i]) return;
-    if (p != INT_MAX) {
-        const uint32_t x = row[j];
-        if (x) {
-            const uint16_t* prow = work + (r + p) * kPanel;
-            const uint32_t factor = fmul(F, x, finv(F, prow[j]));
-            for (int c = j + 1; c < bc; ++c) row[c] ^= uint16_t(fmul(F, factor, prow[c]));
+    __shared__ uint16_t T[kSelRows * kSelPitch];
+    __shared__ uint16_t sexp[2 * 1023];
+    __shared__ uint16_t slog[1024];
+    __shared__ int pivs[kPanel];
+    __shared__ int plog[kPanel];
+    __shared__ int lead;
+    const int tid = threadIdx.x;
+    const int q = int(F.q);
+    const int64_t slot = int64_t(blockIdx.x) * kSelRows + tid;
+    const int row = slot < ncand ? (in ? in[slot] : int(slot)) : -1;
+    uint16_t* mine = T + tid * kSelPitch;
+    if (row >= 0) {
+        const uint4* src = reinterpret_cast<const uint4*>(orig + (r + row) * kPanel);
+#pragma unroll
+        for (int u = 0; u < kPanel / 8; ++u) {
+            const uint4 x = src[u];
+            const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                mine[8 * u + 2 * h] = uint16_t(w[h]);
+                mine[8 * u + 2 * h + 1] = uint16_t(w[h] >> 16);
+            }
         }
+    } else {
+        for (int c = 0; c < kPanel; ++c) mine[c] = 0;
     }
-    if (j + 1 < bc && row[j + 1] != 0) atomicMin(&st->next[j + 1], int(i));
+    for (int k = tid; k < 2 * q; k += kSelRows) sexp[k] = F.exp[k];
+    for (int k = tid; k <= q; k += kSelRows) slog[k] = F.log[k];
+    if (tid < kPanel) pivs[tid] = INT_MAX;
+    __syncthreads();
+    bool used = row < 0;
+    int npiv = 0;
+    {
+        const uint64_t bal = __ballot(!used && mine[0] != 0);
+        if (bal && tid % 64 == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[0], tid);
+    }
+    for (int j = 0; j < bc; ++j) {
+        __syncthreads();  // pivs[j] is final, rows of step j - 1 are written
+        const int p = pivs[j];
+        if (p == INT_MAX) {  // no pivot in column j: offer column j + 1 as it is
+            const uint64_t bal = __ballot(j + 1 < bc && !used && mine[j + 1] != 0);
+            if (bal && tid % 64 == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[j + 1], tid);
+            continue;
+        }
+        if (tid < bc) {
+            const uint32_t pv = T[p * kSelPitch + tid];
+            plog[tid] = pv ? int(slog[pv]) : -1;
+        }
+        if (tid == 0) lead = q - int(slog[T[p * kSelPitch + j]]);
+        __syncthreads();
+        if (tid == p) {
+            used = true;
+            if (final) {
+                st->rows[npiv] = row;
+                st->cols[npiv] = j;
+            } else {
+                out[int64_t(blockIdx.x) * kPanel + npiv] = row;
+            }
+        }
+        ++npiv;  // uniform across the workgroup
+        bool cand = false;
+        if (!used) {
+            const uint32_t x = mine[j];
+            if (x) {
+                int lf = int(slog[x]) + lead;
+                if (lf >= q) lf -= q;
+                for (int c = j + 1; c < bc; ++c) {
+                    const int pl = plog[c];
+                    if (pl >= 0) mine[c] ^= sexp[lf + pl];
+                }
+            }
+            cand = j + 1 < bc && mine[j + 1] != 0;
+        }
+        const uint64_t bal = __ballot(cand);
+        if (j + 1 < bc && bal && tid % 64 == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[j + 1], tid);
+    }
+    if (tid == 0) {
+        if (final) st->rp = npiv;
+        else
+            for (int t = npiv; t < kPanel; ++t) out[int64_t(blockIdx.x) * kPanel + t] = -1;
+    }
 }
 
 // W = K^{-1}, K[s][t] = orig[r + rows[s]][cols[t]] (rp x rp), by Gauss-Jordan
-// on [K | I] in LDS; W is written as elements, row pitch rp.
+// on [K | I] in LDS; W is written as elements, row pitch rp.  Thread (ty, tx)
+// of the 8 x 128 block handles column tx of rows ty, ty + 8, ...
 __global__ __launch_bounds__(1024) void pivot_inverse_kernel(const uint16_t* orig, int64_t r, const PanelState* st,
-                                                             int wide, void* W, DevField F)
+                                                             int wide, void* W, DevField Fg)
 {
-    __shared__ uint16_t M[kPanel][2 * kPanel + 1];
+    constexpr int kCols = 2 * kPanel, kRowGroups = 1024 / kCols;
+    __shared__ uint16_t M[kPanel][kCols + 1];
+    __shared__ uint16_t sexp[2 * 1023];
+    __shared__ uint16_t slog[1024];
     __shared__ int prow;
+    __shared__ uint32_t pinv;
     const int rp = st->rp;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int idx = tid; idx < rp * 2 * rp; idx += nt) {
-        const int s = idx / (2 * rp), c = idx % (2 * rp);
-        M[s][c] = c < rp ? orig[(r + st->rows[s]) * kPanel + st->cols[c]] : uint16_t(c - rp == s ? 1 : 0);
-    }
+    const int tid = threadIdx.x, tx = tid % kCols, ty = tid / kCols;
+    for (int k = tid; k < int(2 * Fg.q); k += 1024) sexp[k] = Fg.exp[k];
+    for (int k = tid; k <= int(Fg.q); k += 1024) slog[k] = Fg.log[k];
+    const DevField F{sexp, slog, Fg.q};
+    if (tx < 2 * rp)
+        for (int s = ty; s < rp; s += kRowGroups)
+            M[s][tx] = tx < rp ? orig[(r + st->rows[s]) * kPanel + st->cols[tx]] : uint16_t(tx - rp == s ? 1 : 0);
     __syncthreads();
     for (int t = 0; t < rp; ++t) {
         if (tid == 0) {
             int p = t;
             while (p < rp && M[p][t] == 0) ++p;  // K is invertible: a pivot exists
             prow = p < rp ? p : t;
+            pinv = p < rp ? finv(F, M[p][t]) : 0u;
         }
         __syncthreads();
         const int p = prow;
-        if (p != t)
-            for (int c = tid; c < 2 * rp; c += nt) {
-                const uint16_t a = M[p][c];
-                M[p][c] = M[t][c];
-                M[t][c] = a;
-            }
-        __syncthreads();
-        const uint32_t dinv = M[t][t] ? finv(F, M[t][t]) : 0u;
-        __syncthreads();
-        for (int c = tid; c < 2 * rp; c += nt) M[t][c] = uint16_t(fmul(F, dinv, M[t][c]));
-        __syncthreads();
-        for (int idx = tid; idx < rp * 2 * rp; idx += nt) {
-            const int s = idx / (2 * rp), c = idx % (2 * rp);
-            if (s == t) continue;
-            const uint32_t x = M[s][t];
-            if (x && c != t) M[s][c] ^= uint16_t(fmul(F, x, M[t][c]));
+        // swap rows p and t, then scale row t so that its entry t is 1
+        if (ty == 0 && tx < 2 * rp) {
+            const uint16_t a = M[p][tx], b = M[t][tx];
+            M[p][tx] = b;
+            M[t][tx] = uint16_t(fmul(F, pinv, a));
         }
         __syncthreads();
-        for (int s = tid; s < rp; s += nt)
-            if (s != t) M[s][t] = 0;
+        // eliminate column t from the other rows (column t itself last)
+        uint16_t xs[kPanel / kRowGroups];
+#pragma unroll
+        for (int k = 0; k < kPanel / kRowGroups; ++k) {
+            const int s = ty + k * kRowGroups;
+            xs[k] = s < rp ? M[s][t] : 0;
+        }
+        __syncthreads();
+        if (tx < 2 * rp) {
+            const uint32_t pv = M[t][tx];
+#pragma unroll
+            for (int k = 0; k < kPanel / kRowGroups; ++k) {
+                const int s = ty + k * kRowGroups;
+                if (s < rp && s != t && xs[k]) M[s][tx] ^= uint16_t(fmul(F, xs[k], pv));
+            }
+        }
         __syncthreads();
     }
-    for (int idx = tid; idx < rp * rp; idx += nt) {
-        const int s = idx / rp, c = idx % rp;
-        st_el(W, wide, idx, M[s][rp + c]);
-    }
+    if (tx < rp)
+        for (int s = ty; s < rp; s += kRowGroups) st_el(W, wide, int64_t(s) * rp + tx, M[s][rp + tx]);
 }
 
 // G[i][t] = original entry of (new) row i at pivot column t, for all rows:
@@ -274,21 +336,21 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         return GF2E_ERANGE;
     }
 
-    // Buffers: two panel copies, used flags, panel state, permutation, W,
-    // pivot-column gather, and room for rows r..m-1 of columns c0..n-1.
+    // Buffers: the panel copy, two candidate lists of the tournament, panel
+    // state, permutation, W, pivot-column gather, and room for rows r..m-1
+    // of columns c0..n-1.
     auto al = [](int64_t b) { return round_up(b, 256); };
-    const int64_t b_orig = al(m * kPanel * 2), b_used = al(m), b_state = al(sizeof(PanelState)),
-                  b_perm = al(m * 4), b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz),
-                  b_tmp = al(m * n * esz);
-    int rc = ensure_aux(2 * b_orig + b_used + b_state + b_perm + b_w + b_g + b_tmp, s);
+    const int64_t b_orig = al(m * kPanel * 2), b_cand = al(ceil_div(m, kSelRows) * kPanel * 4),
+                  b_state = al(sizeof(PanelState)), b_perm = al(m * 4), b_w = al(int64_t(kPanel) * kPanel * esz),
+                  b_g = al(m * kPanel * esz), b_tmp = al(m * n * esz);
+    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_tmp, s);
     if (rc) return rc;
     uint8_t* base = static_cast<uint8_t*>(aux);
     uint16_t* orig = reinterpret_cast<uint16_t*>(base);
-    uint16_t* work = reinterpret_cast<uint16_t*>(base + b_orig);
-    uint8_t* used = base + 2 * b_orig;
-    PanelState* st = reinterpret_cast<PanelState*>(base + 2 * b_orig + b_used);
-    int* perm = reinterpret_cast<int*>(base + 2 * b_orig + b_used + b_state);
-    uint8_t* W = base + 2 * b_orig + b_used + b_state + b_perm;
+    int* cand[2] = {reinterpret_cast<int*>(base + b_orig), reinterpret_cast<int*>(base + b_orig + b_cand)};
+    PanelState* st = reinterpret_cast<PanelState*>(base + b_orig + 2 * b_cand);
+    int* perm = reinterpret_cast<int*>(base + b_orig + 2 * b_cand + b_state);
+    uint8_t* W = base + b_orig + 2 * b_cand + b_state + b_perm;
     uint8_t* G = W + b_w;
     uint8_t* tmp = G + b_g;
 
@@ -301,12 +363,19 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         const int bc = int(std::min<int64_t>(kPanel, n - c0));
         const int64_t mr = m - r;
         hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s, A->data, lda,
-                           m, c0, bc, wide, orig, work);
-        hipLaunchKernelGGL(panel_reset_kernel, dim3(1), dim3(128), 0, s, st);
-        const dim3 g_rows(unsigned(ceil_div(mr, kStepThreads)));
-        hipLaunchKernelGGL(panel_start_kernel, g_rows, dim3(kStepThreads), 0, s, work, r, m, used, st);
-        for (int j = 0; j < bc; ++j)
-            hipLaunchKernelGGL(panel_step_kernel, g_rows, dim3(kStepThreads), 0, s, work, r, m, j, bc, used, st, F);
+                           m, c0, bc, wide, orig);
+        // Tournament levels until one workgroup holds all candidates.
+        const int* in = nullptr;
+        int64_t ncand = mr;
+        for (int level = 0;; ++level) {
+            const int64_t nb = ceil_div(ncand, kSelRows);
+            int* out = cand[level & 1];
+            hipLaunchKernelGGL(panel_select_kernel, dim3(unsigned(nb)), dim3(kSelRows), 0, s, orig, r, bc, in, ncand,
+                               out, nb == 1 ? 1 : 0, st, F);
+            if (nb == 1) break;
+            in = out;
+            ncand = nb * kPanel;
+        }
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
         if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
