@@ -1,19 +1,20 @@
 /*
  * gf2e.h -- C ABI of the MI355X (gfx950) library for dense matrix
- * multiplication over F_{2^e}, 2 <= e <= 10.
+ * multiplication over F_{2^e}, 2 <= e <= 16.
  *
  * What is computed: C = A * B with A m x k and B k x n over
  * F_{2^e} = F_2[x]/<f> (M4RIE paper, Section 2 for the field and the element
  * encoding, Section 4 Algorithm 1 for the product).  An element is the
  * polynomial sum a_i x^i, stored as the integer sum a_i 2^i: one uint8_t per
- * element when e <= 8, one uint16_t when e is 9 or 10.  f is the full
+ * element when e <= 8, one uint16_t when e is 9..16.  f is the full
  * polynomial with bit e set (x^2+x+1 = 0x7, x^8+x^4+x^3+x^2+1 = 0x11D) and
  * must be irreducible of degree e.
  *
  * How: the Bradshaw-Boothby reduction of Section 5.  Each operand is sliced
  * into e GF(2) bit-planes (Section 3.2), the Karatsuba schedule forms t(e)
- * products of plane sums over GF(2) (t = 3, 6, 9, 15, 18, 24, 27, 36, 45 for
- * e = 2..10), the products are recombined into the 2e-1 coefficients of the
+ * products of plane sums over GF(2) (t = 3, 6, 9, 15, 18, 24, 27, 36, 45, 51,
+ * 54, 66, 72, 78, 81 for e = 2..16; fewer for the fields with a schedule
+ * compiled in), the products are recombined into the 2e-1 coefficients of the
  * polynomial product, reduced modulo f, and clung back into elements.  Every
  * step runs as a HIP kernel on the device; the result is exact and unique.
  *
@@ -47,7 +48,7 @@ extern "C" {
 enum {
     GF2E_OK = 0,
     GF2E_EINVAL = -1,  /* null pointer, bad argument */
-    GF2E_EFIELD = -2,  /* e outside 2..10, or f not an irreducible polynomial of degree e */
+    GF2E_EFIELD = -2,  /* e outside 2..16, or f not an irreducible polynomial of degree e */
     GF2E_ESHAPE = -3,  /* inner/outer dimensions disagree, ld < cols, negative size */
     GF2E_EALIAS = -4,  /* C overlaps A or B */
     GF2E_ERANGE = -5,  /* an input entry is >= 2^e (found on the device) */
@@ -220,7 +221,7 @@ const char* gf2e_strerror(int code);
 
 /* ---- Field and schedule queries (host only; need no GPU) ---------------- */
 
-/* GF2E_OK when 2 <= e <= 10 and f is irreducible of degree e. */
+/* GF2E_OK when 2 <= e <= 16 and f is irreducible of degree e. */
 int gf2e_field_check(int e, uint32_t f);
 
 /* Number t of GF(2) products in the schedule used for (e, f), or < 0. */
@@ -231,12 +232,13 @@ int gf2e_num_products(int e, uint32_t f);
  * result is XOR_{s in m[c]} P_s (c < e).  For the Karatsuba schedule of
  * Section 5, coefficient d of the polynomial product is XOR_{s in w[d]} P_s
  * (d < 2e-1) before reduction modulo f; for a schedule compiled in for this
- * particular f (fewer products, reduction folded in) w is all zero.  Arrays:
- * u, v of length >= t, w of length >= 2e-1, m of length >= e; any may be
- * NULL.  GF2E_SCHEDULE=karatsuba in the environment selects Karatsuba for
- * every field. */
-int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint64_t* w,
-                  uint64_t* m);
+ * particular f (fewer products, reduction folded in) w is all zero.  w and m
+ * are 0/1 matrices, one byte per entry, row-major with t columns:
+ * w[d*t + s] = 1 iff s is in w[d], m[c*t + s] = 1 iff s is in m[c].  Arrays:
+ * u, v of length >= t, w of length >= (2e-1)*t, m of length >= e*t, where
+ * t <= 96 (t(16) = 81); any may be NULL.  GF2E_SCHEDULE=karatsuba in the
+ * environment selects Karatsuba for every field. */
+int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint8_t* w, uint8_t* m);
 
 /* ---- Stage entry points (the steps of gf2e_mul, for tests and composition).
  * Plane layouts (64-bit words, bit b of a word = index 64*word + b):

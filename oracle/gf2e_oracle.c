@@ -2,7 +2,7 @@
  * gf2e_oracle.c -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow, obviously correct CPU reference for dense matrix
- * multiplication over F_{2^e} = F_2[x]/<f>, 2 <= e <= 10.  Only the test
+ * multiplication over F_{2^e} = F_2[x]/<f>, 2 <= e <= 16.  Only the test
  * suite, the smoke check and the benchmark's CPU-baseline leg may load this
  * library; the GPU product path never calls it and shares no code with it.
  *
@@ -21,7 +21,7 @@
  *     against the shift-and-add definition by the test suite.
  *
  * Elements are stored one per uint8_t when e <= 8 and one per uint16_t when
- * e is 9 or 10, row-major with a leading dimension counted in elements.
+ * e is 9..16, row-major with a leading dimension counted in elements.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -106,8 +106,8 @@ int gf2e_oracle_is_primitive(int e, uint32_t f)
 typedef struct {
     int e;
     uint32_t f, gen, q;     /* q = 2^e - 1, the group order */
-    uint16_t log[1024];     /* log[0] = 2q: points into the zero tail of exp */
-    uint16_t exp[4 * 1023 + 1];
+    uint32_t log[65536];    /* log[0] = 2q: points into the zero tail of exp */
+    uint16_t exp[4 * 65535 + 1];
 } field_tables;
 
 /* Build tables with the smallest generator g found by search (f need not be
@@ -115,7 +115,7 @@ typedef struct {
  * from 2q on, so log[a] + log[b] indexes 0 whenever a or b is 0. */
 static int build_tables(int e, uint32_t f, field_tables* T)
 {
-    if (e < 2 || e > 10 || !gf2e_oracle_is_irreducible(e, f)) return ORC_EFIELD;
+    if (e < 2 || e > 16 || !gf2e_oracle_is_irreducible(e, f)) return ORC_EFIELD;
     memset(T, 0, sizeof *T);
     T->e = e; T->f = f; T->q = (1u << e) - 1u;
     uint32_t g = 2;
@@ -125,10 +125,10 @@ static int build_tables(int e, uint32_t f, field_tables* T)
     for (uint32_t i = 0; i < T->q; ++i) {
         T->exp[i] = (uint16_t)x;
         T->exp[i + T->q] = (uint16_t)x;
-        T->log[x] = (uint16_t)i;
+        T->log[x] = i;
         x = gf2e_oracle_mul_def(e, f, x, g);
     }
-    T->log[0] = (uint16_t)(2 * T->q);
+    T->log[0] = 2 * T->q;
     return ORC_OK;
 }
 

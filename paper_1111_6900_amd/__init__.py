@@ -167,18 +167,27 @@ def num_products(e: int, f: int) -> int:
     return rc
 
 
+MAX_PRODUCTS = 96
+
+
 def schedule(e: int, f: int) -> dict:
     """The product schedule used for (e, f): u, v (operand subsets), w
     (polynomial recombination; all zero when the schedule has the reduction
-    folded in) and m (result planes after reduction mod f)."""
+    folded in) and m (result planes after reduction mod f).  w[d] and m[c]
+    are returned as sets of product indices packed into Python ints (bit s
+    for product s)."""
     t = ctypes.c_int(0)
-    u = (ctypes.c_uint32 * 64)()
-    v = (ctypes.c_uint32 * 64)()
-    w = (ctypes.c_uint64 * 32)()
-    m = (ctypes.c_uint64 * 16)()
+    u = (ctypes.c_uint32 * MAX_PRODUCTS)()
+    v = (ctypes.c_uint32 * MAX_PRODUCTS)()
+    w = (ctypes.c_uint8 * (31 * MAX_PRODUCTS))()
+    m = (ctypes.c_uint8 * (16 * MAX_PRODUCTS))()
     _check(lib().gf2e_schedule(e, f, ctypes.byref(t), u, v, w, m), "schedule")
     T = t.value
-    return {"t": T, "u": list(u[:T]), "v": list(v[:T]), "w": list(w[:2 * e - 1]), "m": list(m[:e])}
+
+    def rows(buf, count):
+        return [sum(int(buf[r * T + s]) << s for s in range(T)) for r in range(count)]
+
+    return {"t": T, "u": list(u[:T]), "v": list(v[:T]), "w": rows(w, 2 * e - 1), "m": rows(m, e)}
 
 
 def plane_geometry(e: int, f: int, m: int, k: int, n: int) -> Geometry:
@@ -197,8 +206,8 @@ def kernel_names() -> list:
 # ---------------------------------------------------------------------------
 
 def elem_dtype(e: int):
-    """torch storage type of one element: uint8 for e <= 8, int16 for 9, 10."""
-    return torch.uint8 if e <= 8 else torch.int16
+    """torch storage type of one element: uint8 for e <= 8, uint16 for 9..16."""
+    return torch.uint8 if e <= 8 else torch.uint16
 
 
 def mat(t: torch.Tensor) -> Mat:
@@ -213,7 +222,7 @@ def mat(t: torch.Tensor) -> Mat:
 def _check_elem(t: torch.Tensor, e: int, name: str):
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
-    if not 2 <= e <= 10:
+    if not 2 <= e <= 16:
         return  # the library reports GF2E_EFIELD
     ok = (t.dtype == torch.uint8) if e <= 8 else (t.dtype in (torch.int16, torch.uint16))
     if not ok:

@@ -434,7 +434,7 @@ const char* gf2e_strerror(int code)
     switch (code) {
         case GF2E_OK: return "ok";
         case GF2E_EINVAL: return "invalid argument";
-        case GF2E_EFIELD: return "e must be in 2..10 and f an irreducible polynomial of degree e";
+        case GF2E_EFIELD: return "e must be in 2..16 and f an irreducible polynomial of degree e";
         case GF2E_ESHAPE: return "matrix shapes or leading dimensions do not fit";
         case GF2E_EALIAS: return "output overlaps an input";
         case GF2E_ERANGE: return "an input entry is not an element of F_{2^e} (>= 2^e)";
@@ -454,28 +454,32 @@ int gf2e_num_products(int e, uint32_t f)
     return make_plan(e, f, 1, 1, 1).T;
 }
 
-int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint64_t* w, uint64_t* m)
+int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint8_t* w, uint8_t* m)
 {
     if (!field_ok(e, f)) return GF2E_EFIELD;
     const KernelSchedule S = kernel_schedule(e, schedule_id(e, f));
-    if (t) *t = S.t;
-    for (int s = 0; s < S.t; ++s) {
+    const int T = S.t;
+    if (t) *t = T;
+    for (int s = 0; s < T; ++s) {
         if (u) u[s] = S.u[s];
         if (v) v[s] = S.v[s];
     }
     for (int d = 0; d < 2 * e - 1; ++d)
-        if (w) w[d] = S.w[d];  // zero for a field schedule (reduction folded in)
+        for (int s = 0; s < T; ++s)
+            if (w) w[d * T + s] = uint8_t((S.w[d] >> s) & 1u);  // zero for a field schedule
     if (m) {
-        for (int c = 0; c < e; ++c) m[c] = 0;
+        for (int c = 0; c < e; ++c)
+            for (int s = 0; s < T; ++s) m[c * T + s] = 0;
         if (S.folded) {
-            for (int s = 0; s < S.t; ++s)
+            for (int s = 0; s < T; ++s)
                 for (int c = 0; c < e; ++c)
-                    if ((S.c[s] >> c) & 1u) m[c] |= uint64_t(1) << s;
+                    if ((S.c[s] >> c) & 1u) m[c * T + s] = 1;
         } else {
             for (int d = 0; d < 2 * e - 1; ++d) {
                 const uint32_t col = x_pow_mod(d, f, e);
                 for (int c = 0; c < e; ++c)
-                    if ((col >> c) & 1u) m[c] ^= S.w[d];
+                    if ((col >> c) & 1u)
+                        for (int s = 0; s < T; ++s) m[c * T + s] ^= uint8_t((S.w[d] >> s) & 1u);
             }
         }
     }

@@ -137,8 +137,14 @@ __global__ __launch_bounds__(kSelRows) void panel_select_kernel(const uint16_t* 
     } else {
         for (int c = 0; c < kPanel; ++c) mine[c] = 0;
     }
-    for (int k = tid; k < 2 * q; k += kSelRows) sexp[k] = F.exp[k];
-    for (int k = tid; k <= q; k += kSelRows) slog[k] = F.log[k];
+    // tables in LDS when they fit (e <= 10), else read from the device copy
+    const bool lds_tabs = q <= 1023;
+    if (lds_tabs) {
+        for (int k = tid; k < 2 * q; k += kSelRows) sexp[k] = F.exp[k];
+        for (int k = tid; k <= q; k += kSelRows) slog[k] = F.log[k];
+    }
+    const uint16_t* ex = lds_tabs ? sexp : F.exp;
+    const uint16_t* lg = lds_tabs ? slog : F.log;
     if (tid < kPanel) pivs[tid] = INT_MAX;
     __syncthreads();
     bool used = row < 0;
@@ -157,9 +163,9 @@ __global__ __launch_bounds__(kSelRows) void panel_select_kernel(const uint16_t* 
         }
         if (tid < bc) {
             const uint32_t pv = T[p * kSelPitch + tid];
-            plog[tid] = pv ? int(slog[pv]) : -1;
+            plog[tid] = pv ? int(lg[pv]) : -1;
         }
-        if (tid == 0) lead = q - int(slog[T[p * kSelPitch + j]]);
+        if (tid == 0) lead = q - int(lg[T[p * kSelPitch + j]]);
         __syncthreads();
         if (tid == p) {
             used = true;
@@ -175,11 +181,11 @@ __global__ __launch_bounds__(kSelRows) void panel_select_kernel(const uint16_t* 
         if (!used) {
             const uint32_t x = mine[j];
             if (x) {
-                int lf = int(slog[x]) + lead;
+                int lf = int(lg[x]) + lead;
                 if (lf >= q) lf -= q;
                 for (int c = j + 1; c < bc; ++c) {
                     const int pl = plog[c];
-                    if (pl >= 0) mine[c] ^= sexp[lf + pl];
+                    if (pl >= 0) mine[c] ^= ex[lf + pl];
                 }
             }
             cand = j + 1 < bc && mine[j + 1] != 0;
@@ -208,9 +214,12 @@ __global__ __launch_bounds__(1024) void pivot_inverse_kernel(const uint16_t* ori
     __shared__ uint32_t pinv;
     const int rp = st->rp;
     const int tid = threadIdx.x, tx = tid % kCols, ty = tid / kCols;
-    for (int k = tid; k < int(2 * Fg.q); k += 1024) sexp[k] = Fg.exp[k];
-    for (int k = tid; k <= int(Fg.q); k += 1024) slog[k] = Fg.log[k];
-    const DevField F{sexp, slog, Fg.q};
+    const bool lds_tabs = Fg.q <= 1023;  // tables in LDS when they fit (e <= 10)
+    if (lds_tabs) {
+        for (int k = tid; k < int(2 * Fg.q); k += 1024) sexp[k] = Fg.exp[k];
+        for (int k = tid; k <= int(Fg.q); k += 1024) slog[k] = Fg.log[k];
+    }
+    const DevField F = lds_tabs ? DevField{sexp, slog, Fg.q} : Fg;
     if (tx < 2 * rp)
         for (int s = ty; s < rp; s += kRowGroups)
             M[s][tx] = tx < rp ? orig[(r + st->rows[s]) * kPanel + st->cols[tx]] : uint16_t(tx - rp == s ? 1 : 0);

@@ -14,9 +14,9 @@
 //   * a 3-way split with six block products,
 //     c0 = P00, c1 = P01+P00+P11, c2 = P02+P00+P11+P22, c3 = P12+P11+P22,
 //     c4 = P22,
-// taking whichever needs fewer products.  Counts for n = 2..10 are
-// 3, 6, 9, 15, 18, 24, 27, 36, 45 (the paper's Table 3 lists 3, 6, 9 and 27
-// as the best known for n = 2, 3, 4, 8).
+// taking whichever needs fewer products.  Counts for n = 2..16 are
+// 3, 6, 9, 15, 18, 24, 27, 36, 45, 51, 54, 66, 72, 78, 81 (the paper's Table 3
+// lists 3, 6, 9 and 27 as the best known for n = 2, 3, 4, 8).
 //
 // Everything here is constexpr so that the device kernels can take the
 // schedule as compile-time constants; the host library uses the same
@@ -26,16 +26,20 @@
 
 namespace gf2e {
 
-constexpr int kMaxE = 10;
-constexpr int kMaxT = 64;
+constexpr int kMaxE = 16;
+constexpr int kMaxT = 96;  // t(16) = 81
 constexpr int kMaxD = 2 * kMaxE - 1;
+
+// A set of products s < kMaxT, one bit each.
+using ProductMask = unsigned __int128;
+constexpr ProductMask product_bit(int s) { return ProductMask(1) << s; }
 
 struct Schedule {
     int n = 0;
     int t = 0;
     uint32_t u[kMaxT] = {};
     uint32_t v[kMaxT] = {};
-    uint64_t w[kMaxD] = {};
+    ProductMask w[kMaxD] = {};
 };
 
 constexpr int split2_count(int n, int lo);
@@ -100,7 +104,7 @@ constexpr Schedule build_schoolbook(int n)
         for (int j = 0; j < n; ++j) {
             s.u[s.t] = 1u << i;
             s.v[s.t] = 1u << j;
-            s.w[i + j] ^= uint64_t(1) << s.t;
+            s.w[i + j] ^= product_bit(s.t);
             ++s.t;
         }
     return s;
@@ -206,7 +210,7 @@ struct KernelSchedule {
     int t = 0;
     bool folded = false;
     uint32_t u[kMaxT] = {}, v[kMaxT] = {}, c[kMaxT] = {};
-    uint64_t w[kMaxD] = {};
+    ProductMask w[kMaxD] = {};
 };
 
 constexpr KernelSchedule kernel_schedule(int e, int sid)

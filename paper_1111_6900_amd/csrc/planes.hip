@@ -195,32 +195,28 @@ __device__ __attribute__((always_inline)) inline void combine_word(const uint64_
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     constexpr KernelSchedule S = kernel_schedule(E, SID);
     constexpr int D = 2 * E - 1;
-    uint64_t p[S.t];
-#pragma unroll
-    for (int s = 0; s < S.t; ++s) p[s] = k0 ? 0ull : P[s * pstride + i * ldp + w];
-
+    // Products are streamed into the planes they feed, so only the 2e-1
+    // coefficient planes (or e result planes) are live, whatever t is.
     uint64_t c[D];
-    if constexpr (S.folded) {
-        // The schedule already reduces modulo its f: plane q is the XOR of
-        // the products whose output set holds q.
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            uint64_t x = 0;
+    for (int d = 0; d < D; ++d) c[d] = 0;
 #pragma unroll
-            for (int s = 0; s < S.t; ++s)
-                if ((S.c[s] >> q) & 1u) x ^= p[s];
-            c[q] = x;
+    for (int s = 0; s < S.t; ++s) {
+        const uint64_t ps = k0 ? 0ull : P[s * pstride + i * ldp + w];
+        if constexpr (S.folded) {
+            // The schedule already reduces modulo its f: plane q is the XOR
+            // of the products whose output set holds q.
+#pragma unroll
+            for (int q = 0; q < E; ++q)
+                if ((S.c[s] >> q) & 1u) c[q] ^= ps;
+        } else {
+            // Coefficient planes of the polynomial product: C~_d = XOR_{s in w[d]} P_s.
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                if ((S.w[d] >> s) & 1u) c[d] ^= ps;
         }
-    } else {
-        // Coefficient planes of the polynomial product: C~_d = XOR_{s in w[d]} P_s.
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            uint64_t x = 0;
-#pragma unroll
-            for (int s = 0; s < S.t; ++s)
-                if ((S.w[d] >> s) & 1u) x ^= p[s];
-            c[d] = x;
-        }
+    }
+    if constexpr (!S.folded) {
         // Reduction modulo f: x^d = x^(d-E) * (f - x^E) for d >= E, highest first.
         uint64_t fm[E];
 #pragma unroll
@@ -324,63 +320,55 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(
 // Batched forms: blockIdx.y selects the product, blockIdx.x a 256-thread job
 // of that product (blocks past the product's job count return at once).
 // ---------------------------------------------------------------------------
-// Calls fn.template operator()<E, SID>() for the schedule of (e, sid): the
-// Karatsuba schedules (sid < 0) for e = 2..10, or field schedule sid.
-template <int I, class Fn>
+// Calls fn.template operator()<E>() for e in [E, EMAX].
+template <int E, int EMAX, class Fn>
+__host__ __device__ inline bool with_e_in(int e, Fn&& fn)
+{
+    if constexpr (E > EMAX) {
+        return false;
+    } else {
+        if (e == E) {
+            fn.template operator()<E>();
+            return true;
+        }
+        return with_e_in<E + 1, EMAX>(e, fn);
+    }
+}
+
+template <class Fn>
+__host__ __device__ inline bool with_e(int e, Fn&& fn)
+{
+    return with_e_in<2, kMaxE>(e, fn);
+}
+
+// Calls fn.template operator()<E, SID>() for the schedule of (e, sid): field
+// schedule sid (>= 0, when its e is in [EMIN, EMAX]) or the Karatsuba
+// schedule (sid < 0) for e in [EMIN, EMAX].
+template <int I, int EMIN, int EMAX, class Fn>
 __host__ __device__ inline bool with_field_schedule(int sid, Fn& fn)
 {
     if constexpr (I < kNumFieldSchedules) {
-        if (sid == I) {
-            fn.template operator()<kFieldSchedules[I].e, I>();
-            return true;
+        if constexpr (kFieldSchedules[I].e >= EMIN && kFieldSchedules[I].e <= EMAX) {
+            if (sid == I) {
+                fn.template operator()<kFieldSchedules[I].e, I>();
+                return true;
+            }
         }
-        return with_field_schedule<I + 1>(sid, fn);
+        return with_field_schedule<I + 1, EMIN, EMAX>(sid, fn);
     } else {
         return false;
     }
 }
 
-// Calls fn.template operator()<E>() for e = 2..10.
-template <class Fn>
-__host__ __device__ inline bool with_e(int e, Fn&& fn)
+template <int EMIN = 2, int EMAX = kMaxE, class Fn>
+__host__ __device__ inline bool with_schedule(int e, int sid, Fn&& fn)
 {
-    switch (e) {
-        case 2: fn.template operator()<2>(); return true;
-        case 3: fn.template operator()<3>(); return true;
-        case 4: fn.template operator()<4>(); return true;
-        case 5: fn.template operator()<5>(); return true;
-        case 6: fn.template operator()<6>(); return true;
-        case 7: fn.template operator()<7>(); return true;
-        case 8: fn.template operator()<8>(); return true;
-        case 9: fn.template operator()<9>(); return true;
-        case 10: fn.template operator()<10>(); return true;
-        default: return false;
-    }
+    if (sid >= 0) return with_field_schedule<0, EMIN, EMAX>(sid, fn);
+    return with_e_in<EMIN, EMAX>(e, [&]<int E>() { fn.template operator()<E, -1>(); });
 }
 
 // As with_schedule, and sid = kIdentitySchedule too (host launches only, so
 // the batched kernels do not carry the identity instantiations).
-template <class Fn>
-inline bool with_any_schedule(int e, int sid, Fn&& fn);
-
-template <class Fn>
-__host__ __device__ inline bool with_schedule(int e, int sid, Fn&& fn)
-{
-    if (sid >= 0) return with_field_schedule<0>(sid, fn);
-    switch (e) {
-        case 2: fn.template operator()<2, -1>(); return true;
-        case 3: fn.template operator()<3, -1>(); return true;
-        case 4: fn.template operator()<4, -1>(); return true;
-        case 5: fn.template operator()<5, -1>(); return true;
-        case 6: fn.template operator()<6, -1>(); return true;
-        case 7: fn.template operator()<7, -1>(); return true;
-        case 8: fn.template operator()<8, -1>(); return true;
-        case 9: fn.template operator()<9, -1>(); return true;
-        case 10: fn.template operator()<10, -1>(); return true;
-        default: return false;
-    }
-}
-
 template <class Fn>
 inline bool with_any_schedule(int e, int sid, Fn&& fn)
 {
@@ -389,15 +377,22 @@ inline bool with_any_schedule(int e, int sid, Fn&& fn)
     return with_schedule(e, sid, fn);
 }
 
+// The batched kernels are instantiated for two ranges of e, so that the
+// large fields do not raise the register use of the kernels that serve the
+// common small ones; each launch skips the products outside its range.
+constexpr int kSmallE = 10;
+
+template <int EMIN, int EMAX>
 __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProduct* __restrict__ prods,
                                                                  int* __restrict__ err)
 {
     const BatchProduct& P = prods[blockIdx.y];
+    if (P.e < EMIN || P.e > EMAX) return;
     int64_t job = blockIdx.x;
     if (job < P.slice_a_blocks) {
         const int64_t rb_count = P.Mp / kThreads;
         const int64_t r = (job % rb_count) * kThreads + threadIdx.x, kw = job / rb_count;
-        with_schedule(P.e, P.sid, [&]<int E, int SID>() {
+        with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
             slice_row_word<E, SID>(P.A, P.lda, P.m, P.k, P.Apl, P.Mp, P.K64p, err, r, kw);
         });
         return;
@@ -406,21 +401,23 @@ __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProd
     if (job < P.slice_b_blocks) {
         const int64_t cb_count = P.Np / kThreads;
         const int64_t j = (job % cb_count) * kThreads + threadIdx.x, kw = job / cb_count;
-        with_schedule(P.e, P.sid, [&]<int E, int SID>() {
+        with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
             slice_col_word<E, SID>(P.B, P.ldb, P.k, P.n, P.Bpl, P.Np, P.K64p, err, j, kw);
         });
     }
 }
 
+template <int EMIN, int EMAX>
 __global__ __launch_bounds__(kThreads) void batched_combine_kernel(const BatchProduct* __restrict__ prods)
 {
     const BatchProduct& P = prods[blockIdx.y];
+    if (P.e < EMIN || P.e > EMAX) return;
     if (int64_t(blockIdx.x) >= P.combine_blocks) return;
     const int64_t nw = (P.n + 63) / 64;
     const int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (idx >= P.m * nw) return;
     const int64_t i = idx / nw, w = idx % nw;
-    with_schedule(P.e, P.sid, [&]<int E, int SID>() {
+    with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
         combine_word<E, SID>(P.P, P.Mp * (P.Np / 64), P.Np / 64, P.n, P.f, P.C, P.ldc, i, w, P.k == 0);
     });
 }
@@ -533,14 +530,18 @@ hipError_t launch_batched_slice(const BatchProduct* prods, int count, int max_bl
                                 hipStream_t s)
 {
     if (count <= 0 || max_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batched_slice_kernel, dim3(max_blocks, count), dim3(kThreads), 0, s, prods, err);
+    hipLaunchKernelGGL((batched_slice_kernel<2, kSmallE>), dim3(max_blocks, count), dim3(kThreads), 0, s, prods, err);
+    hipLaunchKernelGGL((batched_slice_kernel<kSmallE + 1, kMaxE>), dim3(max_blocks, count), dim3(kThreads), 0, s,
+                       prods, err);
     return hipGetLastError();
 }
 
 hipError_t launch_batched_combine(const BatchProduct* prods, int count, int max_blocks, hipStream_t s)
 {
     if (count <= 0 || max_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batched_combine_kernel, dim3(max_blocks, count), dim3(kThreads), 0, s, prods);
+    hipLaunchKernelGGL((batched_combine_kernel<2, kSmallE>), dim3(max_blocks, count), dim3(kThreads), 0, s, prods);
+    hipLaunchKernelGGL((batched_combine_kernel<kSmallE + 1, kMaxE>), dim3(max_blocks, count), dim3(kThreads), 0, s,
+                       prods);
     return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@
 // with Newton-John tables.  Here the solve is blocked for the GPU:
 //   1. one kernel inverts all 128 x 128 diagonal blocks of T at once (one
 //      workgroup per block, one thread per column of the inverse, field
-//      products by log/antilog tables in LDS);
+//      products by log/antilog tables, in LDS for e <= 10);
 //   2. a recursion over block ranges turns the rest into products on the
 //      bitsliced path: for upper T,
 //          X2 = solve(T22, B2);  B1 += T12 * X2;  X1 = solve(T11, B1),
@@ -28,55 +28,35 @@ namespace {
 
 constexpr int kTrsmBlock = 128;  // diagonal block size = threads per workgroup
 
-__device__ inline uint32_t polymul_dev(uint32_t a, uint32_t b, uint32_t f, int e)
-{
-    uint32_t r = 0;
-    while (b) {
-        if (b & 1u) r ^= a;
-        b >>= 1;
-        a <<= 1;
-        if ((a >> e) & 1u) a ^= f;
-    }
-    return r;
-}
-
-// Log/antilog tables of F_{2^E}: exp[i] = g^i for i < 2q (q = 2^E - 1), log
-// the inverse map on nonzero elements.
+// Log/antilog tables of F_{2^E} (exp[i] = g^i for i < 2q, q = 2^E - 1; log
+// the inverse map on nonzero elements), staged in LDS for E <= 10 and read
+// from the device copy otherwise.
 template <int E>
 struct FieldTabs {
     static constexpr int Q = (1 << E) - 1;
-    uint16_t exp[2 * Q];
-    uint16_t log[Q + 1];
+    static constexpr bool kInLds = E <= 10;
+    uint16_t exp[kInLds ? 2 * Q : 1];
+    uint16_t log[kInLds ? Q + 1 : 1];
+    const uint16_t* gexp;
+    const uint16_t* glog;
 
-    __device__ uint32_t mul(uint32_t a, uint32_t b) const { return (a && b) ? exp[log[a] + log[b]] : 0u; }
-    __device__ uint32_t inv(uint32_t a) const { return exp[Q - log[a]]; }  // a != 0
-};
-
-// Every thread fills a run of consecutive powers, starting from g^start by
-// square and multiply.
-template <int E>
-__device__ void build_tabs(FieldTabs<E>& T, uint32_t f, uint32_t g)
-{
-    constexpr int Q = FieldTabs<E>::Q;
-    const int per = (Q + int(blockDim.x) - 1) / int(blockDim.x);
-    const int i0 = int(threadIdx.x) * per;
-    if (i0 < Q) {
-        uint32_t x = 1, base = g;
-        for (int b = i0; b; b >>= 1) {
-            if (b & 1) x = polymul_dev(x, base, f, E);
-            base = polymul_dev(base, base, f, E);
+    __device__ void load(const uint16_t* dexp, const uint16_t* dlog)
+    {
+        if constexpr (kInLds) {
+            for (int i = threadIdx.x; i < 2 * Q; i += blockDim.x) exp[i] = dexp[i];
+            for (int i = threadIdx.x; i <= Q; i += blockDim.x) log[i] = dlog[i];
         }
-        const int i1 = i0 + per < Q ? i0 + per : Q;
-        for (int i = i0; i < i1; ++i) {
-            T.exp[i] = uint16_t(x);
-            T.exp[i + Q] = uint16_t(x);
-            T.log[x] = uint16_t(i);
-            x = polymul_dev(x, g, f, E);
+        if (threadIdx.x == 0) {
+            gexp = dexp;
+            glog = dlog;
         }
+        __syncthreads();
     }
-    if (threadIdx.x == 0) T.log[0] = 0;  // never used: mul tests for zero
-    __syncthreads();
-}
+    __device__ uint32_t ex(int i) const { return kInLds ? exp[i] : gexp[i]; }
+    __device__ uint32_t lg(uint32_t a) const { return kInLds ? log[a] : glog[a]; }
+    __device__ uint32_t mul(uint32_t a, uint32_t b) const { return (a && b) ? ex(lg(a) + lg(b)) : 0u; }
+    __device__ uint32_t inv(uint32_t a) const { return ex(Q - lg(a)); }  // a != 0
+};
 
 // Inverse of diagonal block q of T (rows and columns [128q, 128q + bs)),
 // written row-major with leading dimension 128 at Tinv + 128q*128.  Thread c
@@ -85,15 +65,16 @@ __device__ void build_tabs(FieldTabs<E>& T, uint32_t f, uint32_t g)
 // err |= 1 for an entry >= 2^E, err |= 2 for a zero on the diagonal.
 template <int E>
 __global__ __launch_bounds__(kTrsmBlock) void trsm_invert_kernel(const void* __restrict__ Tm, int64_t ldt,
-                                                                 int64_t m, int lower, int unit, uint32_t f,
-                                                                 uint32_t g, void* __restrict__ Tinv,
-                                                                 int* __restrict__ err)
+                                                                 int64_t m, int lower, int unit,
+                                                                 const uint16_t* __restrict__ dexp,
+                                                                 const uint16_t* __restrict__ dlog,
+                                                                 void* __restrict__ Tinv, int* __restrict__ err)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     __shared__ FieldTabs<E> tabs;
     __shared__ uint16_t Ts[kTrsmBlock][kTrsmBlock + 1];
     __shared__ uint16_t Xs[kTrsmBlock][kTrsmBlock + 1];
-    build_tabs<E>(tabs, f, g);
+    tabs.load(dexp, dlog);
 
     const int64_t r0 = int64_t(blockIdx.x) * kTrsmBlock;
     const int bs = int(m - r0 < kTrsmBlock ? m - r0 : kTrsmBlock);
@@ -137,34 +118,31 @@ __global__ __launch_bounds__(kTrsmBlock) void trsm_invert_kernel(const void* __r
         for (int i = 0; i < bs; ++i) out[(r0 + i) * kTrsmBlock + c] = elem_t(Xs[i][c]);
 }
 
-template <class Fn>
-bool with_e_host(int e, Fn&& fn)
+template <int E, class Fn>
+bool with_e_host(int e, Fn& fn)
 {
-    switch (e) {
-        case 2: fn.template operator()<2>(); return true;
-        case 3: fn.template operator()<3>(); return true;
-        case 4: fn.template operator()<4>(); return true;
-        case 5: fn.template operator()<5>(); return true;
-        case 6: fn.template operator()<6>(); return true;
-        case 7: fn.template operator()<7>(); return true;
-        case 8: fn.template operator()<8>(); return true;
-        case 9: fn.template operator()<9>(); return true;
-        case 10: fn.template operator()<10>(); return true;
-        default: return false;
+    if constexpr (E > kMaxE) {
+        return false;
+    } else {
+        if (e == E) {
+            fn.template operator()<E>();
+            return true;
+        }
+        return with_e_host<E + 1>(e, fn);
     }
 }
 
-hipError_t launch_trsm_invert(int e, uint32_t f, int lower, int unit, const void* T, int64_t ldt, int64_t m,
-                              void* Tinv, int* err, hipStream_t s)
+hipError_t launch_trsm_invert(int e, const uint16_t* tabs, int lower, int unit, const void* T, int64_t ldt,
+                              int64_t m, void* Tinv, int* err, hipStream_t s)
 {
     if (m <= 0) return hipSuccess;
-    const uint32_t g = find_generator(e, f);
+    const uint32_t q = (1u << e) - 1u;
     const dim3 grid(unsigned(ceil_div(m, kTrsmBlock)));
-    if (!with_e_host(e, [&]<int E>() {
-            hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kTrsmBlock), 0, s, T, ldt, m, lower, unit, f, g,
-                               Tinv, err);
-        }))
-        return hipErrorInvalidValue;
+    auto go = [&]<int E>() {
+        hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kTrsmBlock), 0, s, T, ldt, m, lower, unit, tabs,
+                           tabs + 2 * q, Tinv, err);
+    };
+    if (!with_e_host<2>(e, go)) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -214,7 +192,9 @@ int Ctx::trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32
     if (rc) return rc;
     uint8_t* Tinv = static_cast<uint8_t*>(aux);
     uint8_t* tmp = Tinv + inv_bytes;
-    if (launch_trsm_invert(e, f, lower, unit, T->data, T->ld, m, Tinv, d_err, s) != hipSuccess) return GF2E_EDEVICE;
+    const uint16_t* tabs = field_tables(e, f);
+    if (!tabs) return GF2E_ENOMEM;
+    if (launch_trsm_invert(e, tabs, lower, unit, T->data, T->ld, m, Tinv, d_err, s) != hipSuccess) return GF2E_EDEVICE;
 
     const gf2e_mat inv_all{Tinv, nb * kTrsmBlock, kTrsmBlock, kTrsmBlock};
     // Solve block rows [q0, q1).

@@ -59,14 +59,16 @@ def test_field_check():
         assert g.field_check(e, f)
     assert g.field_check(4, 0x1F)       # irreducible, not primitive
     assert g.field_check(8, 0x11B)      # AES polynomial
-    for e, f in [(2, 0x5), (4, 0x11), (8, 0x101), (3, 0x13), (1, 0x3), (11, 0x805), (16, 0x1002B)]:
+    for e, f in workload.WIDE_POLY.items():
+        assert g.field_check(e, f), (e, hex(f))
+    for e, f in [(2, 0x5), (4, 0x11), (8, 0x101), (3, 0x13), (1, 0x3), (16, 0x10001), (17, 0x20009)]:
         assert not g.field_check(e, f), (e, hex(f))
 
 
 def test_field_check_agrees_with_trial_division():
     from tests import fielddef
     g = _gf2e()
-    for e in range(2, 11):
+    for e in range(2, 13):
         for f in range(1 << e, 1 << (e + 1)):
             assert g.field_check(e, f) == fielddef.is_irreducible(e, f), (e, hex(f))
 
@@ -80,10 +82,12 @@ def _xpow_mod(d, f, e):
     return r
 
 
-KARATSUBA_COUNTS = {2: 3, 3: 6, 4: 9, 5: 15, 6: 18, 7: 24, 8: 27, 9: 36, 10: 45}
+KARATSUBA_COUNTS = {2: 3, 3: 6, 4: 9, 5: 15, 6: 18, 7: 24, 8: 27, 9: 36, 10: 45,
+                    11: 51, 12: 54, 13: 66, 14: 72, 15: 78, 16: 81}
 
 
-@pytest.mark.parametrize("e,f", sorted(workload.DEFAULT_POLY.items()) + [(4, 0x1F), (8, 0x11B)])
+@pytest.mark.parametrize("e,f", sorted(workload.DEFAULT_POLY.items()) + sorted(workload.WIDE_POLY.items())
+                         + [(4, 0x1F), (8, 0x11B)])
 def test_schedule_tensor_identity(e, f):
     """Bilinear identity: for all i, j < e, the products with i in u_s and j
     in v_s add up, through the reduced map m, to the bits of x^(i+j) mod f;
@@ -117,8 +121,8 @@ def test_schedule_counts_against_table3():
     table3 = {2: 3, 3: 6, 4: 9, 5: 13, 6: 17, 7: 22, 8: 27}
     for e, best in table3.items():
         assert g.num_products(e, workload.DEFAULT_POLY[e]) <= best, e
-    for e in range(2, 11):
-        assert g.num_products(e, workload.DEFAULT_POLY[e]) < e * e
+    for e, f in list(workload.DEFAULT_POLY.items()) + list(workload.WIDE_POLY.items()):
+        assert g.num_products(e, f) < e * e
     # A field with no compiled-in schedule uses Karatsuba.
     assert g.num_products(4, 0x1F) == 9 and g.num_products(8, 0x11B) == 27
 

@@ -257,7 +257,7 @@ def test_errors(g, ctx):
         ctx.mul(A, B, e, 0x11)                      # reducible f
     assert ei.value.code == g.EFIELD
     with pytest.raises(g.GF2EError) as ei:
-        ctx.mul(A, B, 11, 0x805)                    # e out of range
+        ctx.mul(A, B, 17, 0x20009)                  # e out of range
     assert ei.value.code == g.EFIELD
     with pytest.raises(g.GF2EError) as ei:
         ctx.mul(A, dev(np.ones((9, 12)), e), e, f)  # inner dimensions

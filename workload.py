@@ -17,6 +17,10 @@ import numpy as np
 # pentanomials.  Primitivity is verified by the test suite, not assumed.
 DEFAULT_POLY = {2: 0x7, 3: 0xB, 4: 0x13, 5: 0x25, 6: 0x43, 7: 0x83, 8: 0x11D,
                 9: 0x211, 10: 0x409}
+# Fields past the paper's range (its Section 1 footnote: the method extends
+# to e <= 16): primitive polynomials x^11+x^2+1, x^12+x^6+x^4+x+1,
+# x^13+x^4+x^3+x+1, x^14+x^10+x^6+x+1, x^15+x+1, x^16+x^12+x^3+x+1.
+WIDE_POLY = {11: 0x805, 12: 0x1053, 13: 0x201B, 14: 0x4443, 15: 0x8003, 16: 0x1100B}
 
 BASE_SEED = 20260
 
