@@ -69,6 +69,7 @@ def parse_args():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-trsm", action="store_true")
     ap.add_argument("--no-echelon", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
@@ -202,6 +203,41 @@ def forms_leg(g, torch, workload, log, reps=10):
         res[name] = row
         ctx.close()
         del Ad, Bd, C
+    return res
+
+
+WIDE_CASES = ((12, 4096), (16, 4096))
+
+
+def wide_leg(g, torch, workload, log, reps=10):
+    """Products over fields past the paper's range (e = 12 and 16, 4096^3),
+    autotuned: ms per product and element-MAC/s."""
+    import numpy as np
+    res = {}
+    ctx = g.Context(0, autotune=True)
+    for e, m in WIDE_CASES:
+        f = workload.WIDE_POLY[e]
+        gen = np.random.default_rng(50000 + e)
+        Ad = torch.from_numpy(workload.field_matrix(gen, m, m, e).astype(np.int64)).to(g.elem_dtype(e)).cuda()
+        Bd = torch.from_numpy(workload.field_matrix(gen, m, m, e).astype(np.int64)).to(g.elem_dtype(e)).cuda()
+        C = torch.empty((m, m), dtype=g.elem_dtype(e), device="cuda")
+        for _ in range(2):
+            ctx.mul_async(Ad, Bd, e, f, out=C)
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.mul_async(Ad, Bd, e, f, out=C)
+        e1.record()
+        ctx.sync()
+        ms = e0.elapsed_time(e1) / reps
+        row = {"e": e, "m": m, "k": m, "n": m, "products": g.num_products(e, f), "ms": round(ms, 3),
+               "element_mac_per_s": m ** 3 / (ms / 1e3),
+               "kernel": g.kernel_names()[ctx.chosen_kernel(e, f, m, m, m)]}
+        log(f"wide {row}")
+        res[f"e{e}_{m}"] = row
+        del Ad, Bd, C
+    ctx.close()
     return res
 
 
@@ -374,6 +410,7 @@ def main():
 
     if args.profile_run:
         args.no_cpu = args.no_batched = args.no_serve = args.no_forms = args.no_trsm = args.no_echelon = True
+        args.no_wide = True
         # A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
         # counters calibrate the byte counts read for the product kernels.
         src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
@@ -476,6 +513,8 @@ def main():
 
     if not args.no_forms:
         out["forms"] = forms_leg(g, torch, workload, lambda *a: log(args, *a))
+    if not args.no_wide:
+        out["wide"] = wide_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_trsm:
         out["trsm"] = trsm_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_echelon:

@@ -260,3 +260,36 @@ def test_empty_inner_dimension_gives_zero():
     A = np.zeros((3, 0), dtype=np.uint8)
     B = np.zeros((0, 4), dtype=np.uint8)
     assert (oracle.matmul(A, B, 4, 0x13) == 0).all()
+
+
+# Fields past the paper's range (11 <= e <= 16): the oracle's tables and
+# products against the definitions, on samples (2^(2e) pairs are too many).
+
+@pytest.mark.parametrize("e,f", sorted(workload.WIDE_POLY.items()))
+def test_wide_polynomials_are_primitive(e, f):
+    assert fielddef.is_irreducible(e, f)
+    assert oracle.is_primitive(e, f)
+    assert oracle.order(e, f, 2) == (1 << e) - 1
+
+
+@pytest.mark.parametrize("e,f", sorted(workload.WIDE_POLY.items()))
+def test_wide_antilog_and_products_match_definition(e, f):
+    g = oracle.generator(e, f)
+    ex = oracle.antilog(e, f).astype(np.int64)
+    assert len(ex) == (1 << e) - 1 and len(set(ex.tolist())) == len(ex)
+    gen = np.random.default_rng(e)
+    idx = gen.integers(0, len(ex), 200)
+    for i in idx[:20]:
+        assert ex[(i + 1) % len(ex)] == oracle.mul_def(e, f, int(ex[i]), g)
+    a = gen.integers(0, 1 << e, 5000)
+    b = gen.integers(0, 1 << e, 5000)
+    want = fielddef.mul(a, b, e, f)
+    got = np.array([oracle.mul_def(e, f, int(x), int(y)) for x, y in zip(a[:300], b[:300])])
+    assert (got == want[:300]).all()
+    # the table-based matrix product against the definition, entry by entry
+    A = workload.field_matrix(gen, 7, 11, e).astype(np.int64)
+    B = workload.field_matrix(gen, 11, 5, e).astype(np.int64)
+    C = np.zeros((7, 5), dtype=np.int64)
+    for l in range(11):
+        C ^= fielddef.mul(A[:, l][:, None], B[l][None, :], e, f)
+    assert (oracle.matmul(A, B, e, f) == C).all()
