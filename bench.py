@@ -112,6 +112,21 @@ def cpu_baseline(A, B, e, f, budget_s, workload_mod=None, echelon=False, no_trsm
         dt = time.perf_counter() - t0
         out["trsm"] = {"value": m * m * cols / 2 / dt, "unit": "element-MAC/s",
                        "sample": f"{cols} of {m} columns of the {m}x{m} solve, {dt:.2f} s on {threads} threads"}
+    # One thread on the two smaller plain workloads (the whole 256^3 product
+    # over F_4, a 64-row sample of the 4096^3 product over F_16).
+    one = {}
+    for name, rows in (("f4_256", None), ("f16_4096", 64)):
+        e1, f1, A1, B1 = workload_mod.plain_inputs(name) if workload_mod is not None else (None,) * 4
+        if e1 is None:
+            break
+        r = A1.shape[0] if rows is None else rows
+        t0 = time.perf_counter()
+        oracle.matmul(A1[:r], B1, e1, f1, nthreads=1)
+        dt = time.perf_counter() - t0
+        one[name] = {"value": r * A1.shape[1] * B1.shape[1] / dt, "unit": "element-MAC/s",
+                     "sample": f"{r} of {A1.shape[0]} rows, {dt:.2f} s on 1 thread"}
+    if one:
+        out["one_thread"] = one
     if echelon:
         # The oracle's elimination loop (single-threaded) on a 2048^2 matrix
         # over F_256 drawn like the echelon leg's.
