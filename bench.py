@@ -41,9 +41,10 @@ def kernel_roofline(name):
     raise KeyError(name)
 
 
-def measured_traffic(workload_name, kernel_name):
+def measured_traffic(workload_name, kernel_name, planes):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None if there is none or the kernel source changed since."""
+    or None if there is none, the kernel source changed since, or the
+    launch then covered a different number of plane products."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -51,7 +52,7 @@ def measured_traffic(workload_name, kernel_name):
         src = open(os.path.join(ROOT, entry["source"]), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != entry["source_sha256"]:
+    if hashlib.sha256(src).hexdigest() != entry["source_sha256"] or entry.get("planes") != planes:
         return None
     return entry["traffic_bytes"]
 
@@ -477,7 +478,7 @@ def main():
     achieved = ops / (prod_ms / 1e3) / 1e12
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(args.workload, kname),
+                "traffic": measured_traffic(args.workload, kname, T if form == g.FORM_SCHEDULE else 1),
                 "kernel": kname, "form": ["schedule", "alpha"][form], "avg_launch_ms": round(prod_ms, 4),
                 "algorithmic_ops_per_launch": ops,
                 "algorithmic_bytes_per_launch": plane_bytes}

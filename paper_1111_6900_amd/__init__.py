@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgf2e.so")
 OK, EINVAL, EFIELD, ESHAPE, EALIAS, ERANGE, ENOMEM, EDEVICE, EBUSY, ESINGULAR = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 KERNEL_AUTO, KERNEL_MFMA_256, KERNEL_MFMA_128, KERNEL_MFMA_256x128, KERNEL_MFMA_64, KERNEL_VALU_128, \
-    KERNEL_MFMA_256_W8, KERNEL_FP4_256_W8, KERNEL_FP4_128 = -1, 0, 1, 2, 3, 4, 5, 6, 7
+    KERNEL_MFMA_256_W8, KERNEL_FP4_256_W8, KERNEL_FP4_128, KERNEL_FP4_128_PLANES = -1, 0, 1, 2, 3, 4, 5, 6, 7, 8
 FORM_AUTO, FORM_SCHEDULE, FORM_ALPHA = -1, 0, 1
 STAGE_SLICE_A, STAGE_SLICE_B, STAGE_PRODUCTS, STAGE_COMBINE, STAGE_BATCH = 0, 1, 2, 3, 4
 

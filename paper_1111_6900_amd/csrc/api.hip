@@ -80,7 +80,7 @@ int schedule_id(int e, uint32_t f)
     return karatsuba_only ? -1 : find_field_schedule(e, f);
 }
 
-Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form)
+Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form, bool short_k)
 {
     Plan p{};
     p.e = e;
@@ -89,7 +89,7 @@ Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form)
     p.m = m; p.k = k; p.n = n;
     p.Mp = round_up(std::max<int64_t>(m, 1), kRowAlign);
     p.Np = round_up(std::max<int64_t>(n, 1), kRowAlign);
-    p.K64p = kwords_padded(std::max<int64_t>(k, 1));
+    p.K64p = short_k && k <= 128 ? 2 : kwords_padded(std::max<int64_t>(k, 1));
     if (form == kFormAlpha) {
         p.sid = kIdentitySchedule;
         p.T = e;
@@ -218,8 +218,16 @@ int default_kind(int T, int64_t m, int64_t n)
 
 bool kind_supports(int kind, const Plan& p)
 {
-    const bool fp4 = kind == GEMM_FP4_256x256_W8 || kind == GEMM_FP4_128x128;
+    if (p.gK64p % 4) return kind == GEMM_FP4_128x128_PLANES;  // only it steps 128-bit stages
+    const bool fp4 = kind == GEMM_FP4_256x256_W8 || kind == GEMM_FP4_128x128 || kind == GEMM_FP4_128x128_PLANES;
     return !fp4 || p.gK64p * 64 <= (int64_t(1) << 24);
+}
+
+int supported_kind(int kind, const Plan& p)
+{
+    if (kind_supports(kind, p)) return kind;
+    // k of 128 bits or less, or f32 counts that would not be exact
+    return p.gK64p % 4 ? GEMM_FP4_128x128_PLANES : GEMM_MFMA_256x256_W8;
 }
 
 int Ctx::choose_form(int e, uint32_t f, int64_t m, int64_t k, int64_t n)
@@ -307,7 +315,8 @@ int Ctx::exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const vo
 
 int Ctx::tune_now(int e, uint32_t f, int64_t m, int64_t k, int64_t n, hipStream_t s)
 {
-    const Plan plans[kNumForms] = {make_plan(e, f, m, k, n, kFormSchedule), make_plan(e, f, m, k, n, kFormAlpha)};
+    const Plan plans[kNumForms] = {make_plan(e, f, m, k, n, kFormSchedule, true),
+                                   make_plan(e, f, m, k, n, kFormAlpha, true)};
     int64_t planes = 0;
     for (const Plan& p : plans) planes = std::max(planes, p.a_bytes + p.b_bytes + p.p_bytes);
     const int esz = elem_bytes(e);
@@ -346,7 +355,8 @@ int Ctx::tune_now(int e, uint32_t f, int64_t m, int64_t k, int64_t n, hipStream_
         uint64_t* Bpl = Apl + p.a_bytes / 8;
         uint64_t* P = Bpl + p.b_bytes / 8;
         // Operand planes of this form from the random inputs.
-        if (exec_plan(p, default_kind(p.gT, p.m, p.gn), dA, k, dB, n, dC, n, s) != GF2E_OK) return GF2E_EDEVICE;
+        if (exec_plan(p, supported_kind(default_kind(p.gT, p.m, p.gn), p), dA, k, dB, n, dC, n, s) != GF2E_OK)
+            return GF2E_EDEVICE;
         // Two rounds over all product kernels (the first also brings the
         // clocks up); each keeps its best round.
         float best_ms[GEMM_NUM_KINDS];
@@ -412,9 +422,8 @@ int Ctx::mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* 
         !tune.count(bucket_of(e, f, m, k, n))) {
         if ((rc = tune_now(e, f, m, k, n, s))) return rc;
     }
-    const Plan p = make_plan(e, f, m, k, n, choose_form(e, f, m, k, n));
-    int kind = choose_kind(p);
-    if (!kind_supports(kind, p)) kind = GEMM_MFMA_256x256_W8;  // f32 counts would not be exact
+    const Plan p = make_plan(e, f, m, k, n, choose_form(e, f, m, k, n), true);
+    const int kind = supported_kind(choose_kind(p), p);
     if ((rc = ensure_workspace(p.a_bytes + p.b_bytes + p.p_bytes, s))) return rc;
     return exec_plan(p, kind, A->data, A->ld, B->data, B->ld, C->data, C->ld, s, acc);
 }
@@ -701,9 +710,8 @@ int gf2e_chosen_kernel(gf2e_ctx* handle, int e, uint32_t f, int64_t m, int64_t k
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c) return GF2E_EINVAL;
     if (!field_ok(e, f)) return GF2E_EFIELD;
-    const Plan p = make_plan(e, f, m, k, n, c->choose_form(e, f, m, k, n));
-    const int kind = c->choose_kind(p);
-    return kind_supports(kind, p) ? kind : GEMM_MFMA_256x256_W8;
+    const Plan p = make_plan(e, f, m, k, n, c->choose_form(e, f, m, k, n), true);
+    return supported_kind(c->choose_kind(p), p);
 }
 
 int gf2e_set_form(gf2e_ctx* handle, int form)

@@ -54,11 +54,20 @@ int validate_mul(const gf2e_mat* A, const gf2e_mat* B, const gf2e_mat* C, int e,
 // Schedule for (e, f): the field schedule if one is compiled in (and not
 // disabled with GF2E_SCHEDULE=karatsuba), else -1.
 int schedule_id(int e, uint32_t f);
-Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form = kFormSchedule);
+// short_k: the plain path's plans, where k <= 128 takes K64p = 2 (run by the
+// kernel with 128-bit stages); the stage entry points, batches and served
+// requests keep K64p a multiple of 4.
+Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form = kFormSchedule, bool short_k = false);
 int default_kind(int T, int64_t m, int64_t n);
 bool kind_supports(int kind, const Plan& p);
+int supported_kind(int kind, const Plan& p);  // kind, or a kernel that can run plan p
 
 struct BatchGraph;  // defined in batch.hip
+
+struct DevTables {
+    const uint16_t* exp;
+    const uint32_t* log;
+};
 
 struct Ctx {
     int device = 0;
@@ -114,10 +123,11 @@ struct Ctx {
     int ensure_aux(int64_t bytes, hipStream_t s);
     int trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32_t f, hipStream_t s);
 
-    // Log/antilog tables of F_2[x]/<f> in device memory (exp[2q] then
-    // log[q+1], uint16), built on first use and kept per (e, f).
-    std::map<uint64_t, uint16_t*> ftabs;
-    const uint16_t* field_tables(int e, uint32_t f);
+    // Log/antilog tables of F_2[x]/<f> in device memory, built on first use
+    // and kept per (e, f): exp[4q + 1] (uint16, g^i for i < 2q, then zeros)
+    // and log[q + 1] (uint32, log 0 = 2q), so that exp[log a + log b] = a*b.
+    std::map<uint64_t, void*> ftabs;
+    DevTables field_tables(int e, uint32_t f);  // {nullptr, nullptr} on failure
     // Row echelon form in place (reduced when full); host-synchronous.
     int echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s);
     void release_batches();

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <utility>
 #include <vector>
 
 #include "ctx.hpp"
@@ -39,16 +40,18 @@ namespace {
 
 constexpr int kPanel = 64;  // columns per panel (max pivots per panel)
 
+// Log/antilog tables (Ctx::field_tables): exp[i] = g^i for i < 2q and 0 for
+// 2q <= i <= 4q; log[a] for a != 0, and log[0] = 2q, so that
+// exp[log[a] + log[b]] is the product a*b for all a, b without a branch.
 struct DevField {
-    const uint16_t* exp;  // exp[i] = g^i for i < 2q
-    const uint16_t* log;  // log[a] for a != 0
+    const uint16_t* exp;  // 4q + 1 entries
+    const uint32_t* log;  // q + 1 entries
     uint32_t q;
 };
+constexpr int kMaxLdsQ = 1023;  // tables staged in LDS up to e = 10
+constexpr int kLdsExp = 4 * kMaxLdsQ + 1;
 
-__device__ inline uint32_t fmul(const DevField& F, uint32_t a, uint32_t b)
-{
-    return (a && b) ? F.exp[F.log[a] + F.log[b]] : 0u;
-}
+__device__ inline uint32_t fmul(const DevField& F, uint32_t a, uint32_t b) { return F.exp[F.log[a] + F.log[b]]; }
 __device__ inline uint32_t finv(const DevField& F, uint32_t a) { return F.exp[F.q - F.log[a]]; }
 
 __device__ inline uint32_t ld_el(const void* M, int wide, int64_t i)
@@ -92,107 +95,112 @@ struct PanelState {
     int rp;                // pivots found
 };
 
-// Pivot search by tournament: each workgroup takes up to kSelRows candidate
+// Pivot search by tournament: each workgroup takes up to ROWS candidate
 // rows of the panel (original entries, from orig), eliminates them column by
-// column in LDS and keeps the rows that became pivots (at most kPanel, in
+// column and keeps the rows that became pivots (at most kPanel, in
 // pivot-column order).  Any maximal independent subset of the panel's rows
 // spans its row space, so the rows kept by all workgroups span it too, and a
 // further level over the kept rows (until one workgroup remains) yields a
 // valid pivot set with the panel's pivot columns.  Candidates are row
 // indices relative to r (in == nullptr: rows 0..ncand-1; -1: an empty slot).
 // A workgroup writes its kept rows to out[blockIdx.x*kPanel + t] (-1 past
-// its count); the last level (final) writes the panel state instead.  The
-// kernel is bound by LDS traffic (each step rewrites the remaining columns
-// of every unused row).
-constexpr int kSelRows = 1024;
-constexpr int kSelPitch = kPanel + 2;  // halfwords per LDS row: 33 words, distinct banks
+// its count); the last level (final) writes the panel state instead.
+//
+// Each row is held in registers by PARTS neighbouring lanes of one wave,
+// lane `part` owning columns part, part + PARTS, ...  The column loop is
+// unrolled, so every register index is a constant and the updates of one
+// step are independent of each other; a step costs two barriers and a few
+// LDS round trips (the pivot row's logarithms, the antilog lookups).
+//
+// Before the tournament, one workgroup runs the same elimination on the
+// first rows only.  When they already hold a pivot in every column of the
+// panel (the usual case for a matrix of full rank), no other row can add
+// one, and their pivots are the panel's.
+constexpr int kSelRows = 256;   // rows per workgroup of the tournament
+constexpr int kSelParts = 4;    // lanes per row
+constexpr int kProbeRows = 128; // rows of the probe (2 kPanel: full rank unless the rows are special)
 
-__global__ __launch_bounds__(kSelRows) void panel_select_kernel(const uint16_t* orig, int64_t r, int bc,
-                                                               const int* in, int64_t ncand, int* out, int final,
-                                                               PanelState* st, DevField F)
+template <int ROWS, int PARTS, bool LDS_TABS>
+__global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16_t* orig, int64_t r, int bc,
+                                                                    const int* in, int64_t ncand, int* out, int final,
+                                                                    PanelState* st, DevField F)
 {
-    __shared__ uint16_t T[kSelRows * kSelPitch];
-    __shared__ uint16_t sexp[2 * 1023];
-    __shared__ uint16_t slog[1024];
+    constexpr int NT = ROWS * PARTS, CPT = kPanel / PARTS;
+    static_assert(kPanel % PARTS == 0 && 64 % PARTS == 0 && NT <= 1024, "rows lie within one wave");
+    __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
+    __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
     __shared__ int pivs[kPanel];
     __shared__ int plog[kPanel];
     __shared__ int lead;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, rl = tid / PARTS, part = tid % PARTS, lane = tid & 63;
     const int q = int(F.q);
-    const int64_t slot = int64_t(blockIdx.x) * kSelRows + tid;
+    const int64_t slot = int64_t(blockIdx.x) * ROWS + rl;
     const int row = slot < ncand ? (in ? in[slot] : int(slot)) : -1;
-    uint16_t* mine = T + tid * kSelPitch;
-    if (row >= 0) {
-        const uint4* src = reinterpret_cast<const uint4*>(orig + (r + row) * kPanel);
+    uint32_t v[CPT];  // v[i]: column part + PARTS * i of this row
 #pragma unroll
-        for (int u = 0; u < kPanel / 8; ++u) {
-            const uint4 x = src[u];
-            const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                mine[8 * u + 2 * h] = uint16_t(w[h]);
-                mine[8 * u + 2 * h + 1] = uint16_t(w[h] >> 16);
-            }
-        }
-    } else {
-        for (int c = 0; c < kPanel; ++c) mine[c] = 0;
+    for (int i = 0; i < CPT; ++i) v[i] = row >= 0 ? orig[(r + row) * kPanel + part + PARTS * i] : 0u;
+    // tables in LDS when they fit (e <= 10), else read from the device copy;
+    // a compile-time choice, so that the lookups are LDS (or global) loads
+    if constexpr (LDS_TABS) {
+        for (int k = tid; k <= 4 * q; k += NT) sexp[k] = F.exp[k];
+        for (int k = tid; k <= q; k += NT) slog[k] = F.log[k];
     }
-    // tables in LDS when they fit (e <= 10), else read from the device copy
-    const bool lds_tabs = q <= 1023;
-    if (lds_tabs) {
-        for (int k = tid; k < 2 * q; k += kSelRows) sexp[k] = F.exp[k];
-        for (int k = tid; k <= q; k += kSelRows) slog[k] = F.log[k];
-    }
-    const uint16_t* ex = lds_tabs ? sexp : F.exp;
-    const uint16_t* lg = lds_tabs ? slog : F.log;
+    const uint16_t* ex = LDS_TABS ? sexp : F.exp;
+    const uint32_t* lg = LDS_TABS ? slog : F.log;
     if (tid < kPanel) pivs[tid] = INT_MAX;
     __syncthreads();
     bool used = row < 0;
     int npiv = 0;
-    {
-        const uint64_t bal = __ballot(!used && mine[0] != 0);
-        if (bal && tid % 64 == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[0], tid);
-    }
-    for (int j = 0; j < bc; ++j) {
-        __syncthreads();  // pivs[j] is final, rows of step j - 1 are written
-        const int p = pivs[j];
-        if (p == INT_MAX) {  // no pivot in column j: offer column j + 1 as it is
-            const uint64_t bal = __ballot(j + 1 < bc && !used && mine[j + 1] != 0);
-            if (bal && tid % 64 == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[j + 1], tid);
-            continue;
+    // Offers this row as the pivot of column c (the first row with a nonzero
+    // entry there wins); only the lane owning column c has a say.
+    auto offer = [&](int c, bool nonzero) {
+        const uint64_t bal = __ballot(c < bc && !used && part == c % PARTS && nonzero);
+        if (bal && lane == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[c], rl);
+    };
+    offer(0, v[0] != 0);
+    // Step J eliminates column J; the steps are instantiated one by one, so
+    // that J is a constant in each.
+    auto step = [&]<int J>() {
+        if (J >= bc) return;  // uniform
+        __syncthreads();      // pivs[J] is final; plog and lead of step J - 1 are no longer read
+        const int p = pivs[J];
+        if (p == INT_MAX) {  // no pivot in column J: offer column J + 1 as it is
+            if constexpr (J + 1 < kPanel) offer(J + 1, v[(J + 1) / PARTS] != 0);
+            return;
         }
-        if (tid < bc) {
-            const uint32_t pv = T[p * kSelPitch + tid];
-            plog[tid] = pv ? int(lg[pv]) : -1;
+        if (rl == p) {  // the pivot row publishes the logarithms of its entries (2q for zeros)
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) plog[part + PARTS * i] = int(lg[v[i]]);
+            if (part == J % PARTS) lead = q - int(lg[v[J / PARTS]]);
         }
-        if (tid == 0) lead = q - int(lg[T[p * kSelPitch + j]]);
         __syncthreads();
-        if (tid == p) {
-            used = true;
-            if (final) {
-                st->rows[npiv] = row;
-                st->cols[npiv] = j;
-            } else {
-                out[int64_t(blockIdx.x) * kPanel + npiv] = row;
-            }
-        }
-        ++npiv;  // uniform across the workgroup
-        bool cand = false;
-        if (!used) {
-            const uint32_t x = mine[j];
-            if (x) {
-                int lf = int(lg[x]) + lead;
-                if (lf >= q) lf -= q;
-                for (int c = j + 1; c < bc; ++c) {
-                    const int pl = plog[c];
-                    if (pl >= 0) mine[c] ^= ex[lf + pl];
+        if (rl == p) {
+            if (part == 0) {
+                if (final) {
+                    st->rows[npiv] = row;
+                    st->cols[npiv] = J;
+                } else {
+                    out[int64_t(blockIdx.x) * kPanel + npiv] = row;
                 }
             }
-            cand = j + 1 < bc && mine[j + 1] != 0;
+            used = true;
         }
-        const uint64_t bal = __ballot(cand);
-        if (j + 1 < bc && bal && tid % 64 == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[j + 1], tid);
-    }
+        ++npiv;  // uniform across the workgroup
+        // x: this row's entry in column J, held by the lane owning column J
+        const uint32_t x = __shfl(v[J / PARTS], (lane & ~(PARTS - 1)) | (J % PARTS));
+        // lf: log of the multiplier x / pivot, or 2q (a zero product) for
+        // rows that are used or have nothing to eliminate; no branch per row
+        int lf = int(lg[x]) + lead;
+        lf -= lf >= q ? q : 0;
+        lf = used || x == 0 ? 2 * q : lf;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i)
+            if (part + PARTS * i > J) v[i] ^= ex[lf + plog[part + PARTS * i]];
+        if constexpr (J + 1 < kPanel) offer(J + 1, v[(J + 1) / PARTS] != 0);
+    };
+    [&]<int... J>(std::integer_sequence<int, J...>) {
+        (step.template operator()<J>(), ...);
+    }(std::make_integer_sequence<int, kPanel>{});
     if (tid == 0) {
         if (final) st->rp = npiv;
         else
@@ -201,35 +209,45 @@ __global__ __launch_bounds__(kSelRows) void panel_select_kernel(const uint16_t* 
 }
 
 // W = K^{-1}, K[s][t] = orig[r + rows[s]][cols[t]] (rp x rp), by Gauss-Jordan
-// on [K | I] in LDS; W is written as elements, row pitch rp.  Thread (ty, tx)
-// of the 8 x 128 block handles column tx of rows ty, ty + 8, ...
-__global__ __launch_bounds__(1024) void pivot_inverse_kernel(const uint16_t* orig, int64_t r, const PanelState* st,
-                                                             int wide, void* W, DevField Fg)
+// on [K | I] in LDS; W is written as elements, row pitch rp.  Thread
+// (ty, tx) of the 8 x 128 block handles column tx of rows ty, ty + 8, ...
+// Step t leaves column t of K alone: it is never read again, and since no
+// thread writes it, the multipliers M[s][t] can be read while other
+// columns are updated.
+constexpr int kInvThreads = 1024;
+
+template <bool LDS_TABS>
+__global__ __launch_bounds__(kInvThreads) void pivot_inverse_kernel(const uint16_t* orig, int64_t r,
+                                                                    const PanelState* st, int wide, void* W,
+                                                                    DevField Fg)
 {
-    constexpr int kCols = 2 * kPanel, kRowGroups = 1024 / kCols;
+    constexpr int kCols = 2 * kPanel, kRowGroups = kInvThreads / kCols, RPT = kPanel / kRowGroups;
     __shared__ uint16_t M[kPanel][kCols + 1];
-    __shared__ uint16_t sexp[2 * 1023];
-    __shared__ uint16_t slog[1024];
+    __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
+    __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
     __shared__ int prow;
     __shared__ uint32_t pinv;
     const int rp = st->rp;
     const int tid = threadIdx.x, tx = tid % kCols, ty = tid / kCols;
-    const bool lds_tabs = Fg.q <= 1023;  // tables in LDS when they fit (e <= 10)
-    if (lds_tabs) {
-        for (int k = tid; k < int(2 * Fg.q); k += 1024) sexp[k] = Fg.exp[k];
-        for (int k = tid; k <= int(Fg.q); k += 1024) slog[k] = Fg.log[k];
+    if constexpr (LDS_TABS) {  // tables in LDS when they fit (e <= 10)
+        for (int k = tid; k <= int(4 * Fg.q); k += kInvThreads) sexp[k] = Fg.exp[k];
+        for (int k = tid; k <= int(Fg.q); k += kInvThreads) slog[k] = Fg.log[k];
     }
-    const DevField F = lds_tabs ? DevField{sexp, slog, Fg.q} : Fg;
+    const DevField F = LDS_TABS ? DevField{sexp, slog, Fg.q} : Fg;
     if (tx < 2 * rp)
-        for (int s = ty; s < rp; s += kRowGroups)
-            M[s][tx] = tx < rp ? orig[(r + st->rows[s]) * kPanel + st->cols[tx]] : uint16_t(tx - rp == s ? 1 : 0);
+        for (int s = ty; s < kPanel; s += kRowGroups)  // rows rp.. stay zero
+            M[s][tx] = s >= rp ? uint16_t(0)
+                       : tx < rp ? orig[(r + st->rows[s]) * kPanel + st->cols[tx]]
+                                 : uint16_t(tx - rp == s ? 1 : 0);
     __syncthreads();
     for (int t = 0; t < rp; ++t) {
-        if (tid == 0) {
-            int p = t;
-            while (p < rp && M[p][t] == 0) ++p;  // K is invertible: a pivot exists
-            prow = p < rp ? p : t;
-            pinv = p < rp ? finv(F, M[p][t]) : 0u;
+        if (tid < 64) {  // pivot: the first row s >= t with M[s][t] != 0 (K is invertible)
+            const uint64_t bal = __ballot(tid >= t && tid < rp && M[tid][t] != 0);
+            if (tid == 0) {
+                const int p = bal ? __ffsll(static_cast<long long>(bal)) - 1 : t;
+                prow = p;
+                pinv = bal ? finv(F, M[p][t]) : 0u;
+            }
         }
         __syncthreads();
         const int p = prow;
@@ -240,20 +258,15 @@ __global__ __launch_bounds__(1024) void pivot_inverse_kernel(const uint16_t* ori
             M[t][tx] = uint16_t(fmul(F, pinv, a));
         }
         __syncthreads();
-        // eliminate column t from the other rows (column t itself last)
-        uint16_t xs[kPanel / kRowGroups];
+        // eliminate column t from the other rows (zero entries give a zero
+        // product through log 0 = 2q, so there is no branch per row)
+        if (tx < 2 * rp && tx != t) {
+            const int lp = int(F.log[M[t][tx]]);
 #pragma unroll
-        for (int k = 0; k < kPanel / kRowGroups; ++k) {
-            const int s = ty + k * kRowGroups;
-            xs[k] = s < rp ? M[s][t] : 0;
-        }
-        __syncthreads();
-        if (tx < 2 * rp) {
-            const uint32_t pv = M[t][tx];
-#pragma unroll
-            for (int k = 0; k < kPanel / kRowGroups; ++k) {
+            for (int k = 0; k < RPT; ++k) {
                 const int s = ty + k * kRowGroups;
-                if (s < rp && s != t && xs[k]) M[s][tx] ^= uint16_t(fmul(F, xs[k], pv));
+                const uint32_t x = s == t ? 0u : M[s][t];  // rows s >= rp hold zeros
+                M[s][tx] ^= F.exp[int(F.log[x]) + lp];
             }
         }
         __syncthreads();
@@ -263,7 +276,9 @@ __global__ __launch_bounds__(1024) void pivot_inverse_kernel(const uint16_t* ori
 }
 
 // G[i][t] = original entry of (new) row i at pivot column t, for all rows:
-// rows i < r are unmoved, row r + k is old row r + perm[k].  Pitch rp.
+// rows i < r are unmoved, row r + k is old row r + perm[k], and the pivot
+// rows r..r+rp-1 get zeros (so that one product can update every other row).
+// Pitch rp.
 __global__ void gather_pivot_columns_kernel(const uint16_t* orig, int64_t r, int64_t m, const int* perm,
                                             const PanelState* st, int rp, int wide, void* G)
 {
@@ -271,18 +286,34 @@ __global__ void gather_pivot_columns_kernel(const uint16_t* orig, int64_t r, int
     if (idx >= m * rp) return;
     const int64_t i = idx / rp;
     const int t = int(idx % rp);
+    if (i >= r && i < r + rp) {
+        st_el(G, wide, idx, 0);
+        return;
+    }
     const int64_t src = i < r ? i : r + perm[i - r];
     st_el(G, wide, idx, orig[src * kPanel + st->cols[t]]);
 }
 
-// tmp[k][c] = A[r + perm[k]][c0 + c] for k < rows, c < cols (pitch cols).
-__global__ void gather_rows_kernel(const void* A, int64_t lda, int64_t r, int64_t c0, const int* perm, int64_t rows,
-                                   int64_t cols, int wide, void* tmp)
+// Row moves of one panel on columns c0..c0+cols-1: position r + moves[j]
+// takes old row r + perm[moves[j]].  Gathered into tmp (pitch cols) first,
+// then scattered, since the moves permute the rows among themselves.
+__global__ void gather_rows_kernel(const void* A, int64_t lda, int64_t r, int64_t c0, const int* perm,
+                                   const int* moves, int nmoves, int64_t cols, int wide, void* tmp)
 {
-    for (int64_t k = blockIdx.y; k < rows; k += gridDim.y) {
-        const int64_t src = (r + perm[k]) * lda + c0;
+    for (int64_t j = blockIdx.y; j < nmoves; j += gridDim.y) {
+        const int64_t src = (r + perm[moves[j]]) * lda + c0;
         for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < cols; c += int64_t(gridDim.x) * blockDim.x)
-            st_el(tmp, wide, k * cols + c, ld_el(A, wide, src + c));
+            st_el(tmp, wide, j * cols + c, ld_el(A, wide, src + c));
+    }
+}
+
+__global__ void scatter_rows_kernel(void* A, int64_t lda, int64_t r, int64_t c0, const int* moves, int nmoves,
+                                    int64_t cols, int wide, const void* tmp)
+{
+    for (int64_t j = blockIdx.y; j < nmoves; j += gridDim.y) {
+        const int64_t dst = (r + moves[j]) * lda + c0;
+        for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < cols; c += int64_t(gridDim.x) * blockDim.x)
+            st_el(A, wide, dst + c, ld_el(tmp, wide, j * cols + c));
     }
 }
 
@@ -293,31 +324,40 @@ dim3 rows_grid(int64_t rows, int64_t cols)
 
 }  // namespace
 
-const uint16_t* Ctx::field_tables(int e, uint32_t f)
+DevTables Ctx::field_tables(int e, uint32_t f)
 {
     const uint64_t key = (uint64_t(e) << 32) | f;
-    auto it = ftabs.find(key);
-    if (it != ftabs.end()) return it->second;
     const uint32_t q = (1u << e) - 1u;
-    std::vector<uint16_t> h(2 * q + (q + 1), 0);  // exp[2q] then log[q + 1]
+    const size_t exp_words = round_up(4 * q + 1, 2);  // uint16 entries, padded to 4 bytes
+    auto view = [&](void* d) {
+        return DevTables{static_cast<const uint16_t*>(d),
+                         reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(d) + exp_words)};
+    };
+    auto it = ftabs.find(key);
+    if (it != ftabs.end()) return view(it->second);
+    std::vector<uint16_t> hexp(exp_words, 0);
+    std::vector<uint32_t> hlog(q + 1, 0);
     const uint32_t g = find_generator(e, f);
     uint32_t x = 1;
     for (uint32_t i = 0; i < q; ++i) {
-        h[i] = h[i + q] = uint16_t(x);
-        h[2 * q + x] = uint16_t(i);
+        hexp[i] = hexp[i + q] = uint16_t(x);
+        hlog[x] = i;
         x = polymulmod(x, g, f, e);
     }
+    hlog[0] = 2 * q;
     void* d = nullptr;
-    if (hipMalloc(&d, h.size() * sizeof(uint16_t)) != hipSuccess) {
+    const size_t eb = exp_words * sizeof(uint16_t), lb = hlog.size() * sizeof(uint32_t);
+    if (hipMalloc(&d, eb + lb) != hipSuccess) {
         (void)hipGetLastError();
-        return nullptr;
+        return {nullptr, nullptr};
     }
-    if (hipMemcpy(d, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(d, hexp.data(), eb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(static_cast<uint8_t*>(d) + eb, hlog.data(), lb, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
-        return nullptr;
+        return {nullptr, nullptr};
     }
-    ftabs[key] = static_cast<uint16_t*>(d);
-    return static_cast<uint16_t*>(d);
+    ftabs[key] = d;
+    return view(d);
 }
 
 int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s)
@@ -327,10 +367,10 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     if (m == 0 || n == 0) return GF2E_OK;
     const int wide = e > 8 ? 1 : 0;
     const int esz = elem_bytes(e);
-    const uint16_t* tabs = field_tables(e, f);
-    if (!tabs) return GF2E_ENOMEM;
+    const DevTables tabs = field_tables(e, f);
+    if (!tabs.exp) return GF2E_ENOMEM;
     const uint32_t q = (1u << e) - 1u;
-    const DevField F{tabs, tabs + 2 * q, q};
+    const DevField F{tabs.exp, tabs.log, q};
 
     // Entries >= 2^e: report before touching A.
     int flag = 0;
@@ -346,13 +386,14 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     }
 
     // Buffers: the panel copy, two candidate lists of the tournament, panel
-    // state, permutation, W, pivot-column gather, and room for rows r..m-1
-    // of columns c0..n-1.
+    // state, permutation and row moves, W, pivot-column gather, the reduced
+    // pivot rows X1, and the moved rows of one panel.
     auto al = [](int64_t b) { return round_up(b, 256); };
     const int64_t b_orig = al(m * kPanel * 2), b_cand = al(ceil_div(m, kSelRows) * kPanel * 4),
-                  b_state = al(sizeof(PanelState)), b_perm = al(m * 4), b_w = al(int64_t(kPanel) * kPanel * esz),
-                  b_g = al(m * kPanel * esz), b_tmp = al(m * n * esz);
-    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_tmp, s);
+                  b_state = al(sizeof(PanelState)), b_perm = al((m + 2 * kPanel) * 4),
+                  b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz), b_x1 = al(kPanel * n * esz),
+                  b_mv = al(2 * kPanel * n * esz);
+    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_x1 + b_mv, s);
     if (rc) return rc;
     uint8_t* base = static_cast<uint8_t*>(aux);
     uint16_t* orig = reinterpret_cast<uint16_t*>(base);
@@ -361,82 +402,116 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     int* perm = reinterpret_cast<int*>(base + b_orig + 2 * b_cand + b_state);
     uint8_t* W = base + b_orig + 2 * b_cand + b_state + b_perm;
     uint8_t* G = W + b_w;
-    uint8_t* tmp = G + b_g;
+    uint8_t* x1 = G + b_g;
+    uint8_t* mvbuf = x1 + b_x1;
 
     PanelState hs;
     std::vector<int> hperm;
+    std::vector<char> is_piv;
     uint8_t* Ad = static_cast<uint8_t*>(A->data);
     const int64_t lda = A->ld;
     int64_t r = 0;
+    const bool lds_tabs = q <= kMaxLdsQ;
     for (int64_t c0 = 0; c0 < n && r < m; c0 += kPanel) {
         const int bc = int(std::min<int64_t>(kPanel, n - c0));
         const int64_t mr = m - r;
+        auto launch_select = [&]<int ROWS>(int64_t nb, int64_t ncand, const int* in, int* out, int final) {
+            const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * kSelParts)};
+            if (lds_tabs)
+                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, true>), grid, block, 0, s, orig, r, bc, in,
+                                   ncand, out, final, st, F);
+            else
+                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, false>), grid, block, 0, s, orig, r, bc, in,
+                                   ncand, out, final, st, F);
+        };
         hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s, A->data, lda,
                            m, c0, bc, wide, orig);
-        // Tournament levels until one workgroup holds all candidates.
-        const int* in = nullptr;
-        int64_t ncand = mr;
-        for (int level = 0;; ++level) {
-            const int64_t nb = ceil_div(ncand, kSelRows);
-            int* out = cand[level & 1];
-            hipLaunchKernelGGL(panel_select_kernel, dim3(unsigned(nb)), dim3(kSelRows), 0, s, orig, r, bc, in, ncand,
-                               out, nb == 1 ? 1 : 0, st, F);
-            if (nb == 1) break;
-            in = out;
-            ncand = nb * kPanel;
-        }
+        // Probe on the first rows; the whole tournament only when they lack a
+        // pivot in some column and further rows exist.
+        const int64_t probe = std::min<int64_t>(mr, kProbeRows);
+        launch_select.template operator()<kProbeRows>(1, probe, static_cast<const int*>(nullptr), cand[0], 1);
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
         if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return GF2E_EDEVICE;
+        if (hs.rp < bc && mr > probe) {
+            // Tournament levels until one workgroup holds all candidates.
+            const int* in = nullptr;
+            int64_t ncand = mr;
+            for (int level = 0;; ++level) {
+                const int64_t nb = ceil_div(ncand, kSelRows);
+                int* out = cand[level & 1];
+                launch_select.template operator()<kSelRows>(nb, ncand, in, out, nb == 1 ? 1 : 0);
+                if (nb == 1) break;
+                in = out;
+                ncand = nb * kPanel;
+            }
+            if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
+            if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return GF2E_EDEVICE;
+        }
         const int rp = hs.rp;
         if (rp == 0) continue;
         for (int t = 0; t < rp; ++t)
             if (pivots) pivots[r + t] = c0 + hs.cols[t];
 
-        // New order of rows r..m-1: the pivot rows, then the others in order.
-        hperm.assign(size_t(mr), 0);
-        std::vector<char> is_piv(size_t(mr), 0);
-        for (int t = 0; t < rp; ++t) {
-            hperm[t] = hs.rows[t];
-            is_piv[hs.rows[t]] = 1;
+        // Rows r..r+rp-1 receive the pivot rows; a non-pivot row found there
+        // moves to the place left by a pivot row from further down.  The
+        // order of the non-pivot rows does not matter: they are reduced by
+        // later panels, and the reduced form is unique.
+        hperm.resize(size_t(mr) + 2 * kPanel);
+        for (int64_t i = 0; i < mr; ++i) hperm[i] = int(i);
+        is_piv.assign(size_t(std::min<int64_t>(mr, kPanel)), 0);
+        for (int t = 0; t < rp; ++t)
+            if (hs.rows[t] < rp) is_piv[hs.rows[t]] = 1;
+        int disp[kPanel], nd = 0;
+        for (int k = 0; k < rp; ++k)
+            if (!is_piv[k]) disp[nd++] = k;
+        int* moves = hperm.data() + mr;
+        int nm = 0;
+        for (int t = 0, j = 0; t < rp; ++t) {
+            if (hs.rows[t] != t) moves[nm++] = t;
+            if (hs.rows[t] >= rp) {
+                hperm[hs.rows[t]] = disp[j++];
+                moves[nm++] = hs.rows[t];
+            }
         }
-        int64_t k = rp;
-        for (int64_t i = 0; i < mr; ++i)
-            if (!is_piv[i]) hperm[k++] = int(i);
-        if (hipMemcpyAsync(perm, hperm.data(), size_t(mr) * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        for (int t = 0; t < rp; ++t) hperm[t] = hs.rows[t];
+        if (hipMemcpyAsync(perm, hperm.data(), size_t(mr + nm) * 4, hipMemcpyHostToDevice, s) != hipSuccess)
             return GF2E_EDEVICE;
 
-        hipLaunchKernelGGL(pivot_inverse_kernel, dim3(1), dim3(1024), 0, s, orig, r, st, wide, W, F);
+        if (lds_tabs)
+            hipLaunchKernelGGL(pivot_inverse_kernel<true>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide, W, F);
+        else
+            hipLaunchKernelGGL(pivot_inverse_kernel<false>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide, W, F);
         hipLaunchKernelGGL(gather_pivot_columns_kernel, dim3(unsigned(ceil_div(m * rp, 256))), dim3(256), 0, s, orig,
                            r, m, perm, st, rp, wide, G);
         const int64_t nc = n - c0;
-        hipLaunchKernelGGL(gather_rows_kernel, rows_grid(mr, nc), dim3(256), 0, s, A->data, lda, r, c0, perm, mr, nc,
-                           wide, tmp);
+        if (nm > 0) {
+            hipLaunchKernelGGL(gather_rows_kernel, rows_grid(nm, nc), dim3(256), 0, s, A->data, lda, r, c0, perm,
+                               perm + mr, nm, nc, wide, mvbuf);
+            hipLaunchKernelGGL(scatter_rows_kernel, rows_grid(nm, nc), dim3(256), 0, s, A->data, lda, r, c0,
+                               perm + mr, nm, nc, wide, mvbuf);
+        }
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-        if (hipMemcpy2DAsync(Ad + (r * lda + c0) * esz, size_t(lda * esz), tmp, size_t(nc * esz), size_t(nc * esz),
-                             size_t(mr), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return GF2E_EDEVICE;
 
-        // X1 = W * (pivot rows), written back over them.
+        // X1 = W * (pivot rows); every other row (from r on, or all rows for
+        // the reduced form) += G * X1, where G is zero on the pivot rows;
+        // then X1 replaces the pivot rows.
         const gf2e_mat Wm{W, rp, rp, rp};
         const gf2e_mat P1{Ad + (r * lda + c0) * esz, rp, nc, lda};
-        gf2e_mat X1{tmp, rp, nc, nc};
+        gf2e_mat X1{x1, rp, nc, nc};
         if ((rc = mul(e, f, &Wm, &P1, &X1, s))) return rc;
-        if (hipMemcpy2DAsync(Ad + (r * lda + c0) * esz, size_t(lda * esz), tmp, size_t(nc * esz), size_t(nc * esz),
+        const int64_t lo = full ? 0 : r;
+        if (m - lo > rp) {
+            const gf2e_mat Gm{G + lo * rp * esz, m - lo, rp, rp};
+            gf2e_mat Cm{Ad + (lo * lda + c0) * esz, m - lo, nc, lda};
+            if ((rc = mul(e, f, &Gm, &X1, &Cm, s, true))) return rc;
+        }
+        if (hipMemcpy2DAsync(Ad + (r * lda + c0) * esz, size_t(lda * esz), x1, size_t(nc * esz), size_t(nc * esz),
                              size_t(rp), hipMemcpyDeviceToDevice, s) != hipSuccess)
             return GF2E_EDEVICE;
-        // Rows below: += Z * X1; rows above (reduced form): += Y * X1.
-        if (mr > rp) {
-            const gf2e_mat Z{G + (r + rp) * rp * esz, mr - rp, rp, rp};
-            gf2e_mat Cb{Ad + ((r + rp) * lda + c0) * esz, mr - rp, nc, lda};
-            if ((rc = mul(e, f, &Z, &P1, &Cb, s, true))) return rc;
-        }
-        if (full && r > 0) {
-            const gf2e_mat Y{G, r, rp, rp};
-            gf2e_mat Ca{Ad + c0 * esz, r, nc, lda};
-            if ((rc = mul(e, f, &Y, &P1, &Ca, s, true))) return rc;
-        }
         r += rp;
     }
     *rank = r;

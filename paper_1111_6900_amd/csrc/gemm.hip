@@ -15,6 +15,7 @@
 // VALU path: the same planes, AND/XOR on 32-bit words (acc ^= a & b, one
 // v_bitop3 per 32 bit-products), parity by popcount at the end.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include "gf2e_internal.hpp"
 
@@ -315,6 +316,34 @@ struct Fp4Side<ROWS, CH, kSplit, BSIDE> {
     }
 };
 
+// Writes the parities of a wave's accumulators as plane words: the same
+// output layout and packing as the int8 tile.
+template <int BM, int BN, int WM, int WN>
+__device__ __attribute__((always_inline)) inline void fp4_store_parity(
+    const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], uint64_t* __restrict__ Ps,
+    int64_t Np, int tile_m, int tile_n, int wr, int wc, int lane)
+{
+    constexpr int FM = MfmaTile<BM, BN, WM, WN>::FM, FN = MfmaTile<BM, BN, WM, WN>::FN;
+    const int64_t ldp = Np / 64;
+    const int rg = lane & 3, rr = (lane >> 2) & 3, wsel = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64((int(acc[i][j][r]) & 1) != 0);
+                if (rr == r && wsel == (j >> 2)) word |= ((bal >> (16 * rg)) & 0xFFFFull) << (16 * (j & 3));
+            }
+        if (lane < 16 * (WN / 64)) {
+            const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + 4 * rg + rr;
+            const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + wsel;
+            Ps[row * ldp + colw] = word;
+        }
+    }
+}
+
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
 __device__ __attribute__((always_inline)) inline void fp4_tile(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
@@ -329,7 +358,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
     const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
-    static_assert(KB == 2, "stages are whole 256-bit k-steps (K64p is a multiple of 4)");
+    static_assert(KB == 1 || KB == 2, "a stage is one or two 128-bit k-blocks (K64p a multiple of 2 * KB)");
     static_assert(BM % 64 == 0 && NT % 64 == 0, "a wave stages rows of one side only");
     const int nstages = int(K64p / (2 * KB));
 
@@ -406,25 +435,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
         __syncthreads();
     }
 
-    // Same output layout and packing as the int8 tile.
-    const int64_t ldp = Np / 64;
-    const int rg = lane & 3, rr = (lane >> 2) & 3, wsel = lane >> 4;
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-        uint64_t word = 0;
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint64_t bal = __builtin_amdgcn_ballot_w64((int(acc[i][j][r]) & 1) != 0);
-                if (rr == r && wsel == (j >> 2)) word |= ((bal >> (16 * rg)) & 0xFFFFull) << (16 * (j & 3));
-            }
-        if (lane < 16 * (WN / 64)) {
-            const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + 4 * rg + rr;
-            const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + wsel;
-            Ps[row * ldp + colw] = word;
-        }
-    }
+    fp4_store_parity<BM, BN, WM, WN>(acc, Ps, Np, tile_m, tile_n, wr, wc, lane);
 }
 
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
@@ -435,6 +446,111 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
     const int64_t s = blockIdx.z;
     fp4_tile<BM, BN, WM, WN, KB, FA, FB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
                                  Np, K64p, blockIdx.y, blockIdx.x);
+}
+
+// Products with little k: stages of one 128-bit k-block (K64p a multiple of
+// 2), and each workgroup runs planes s0..s1-1 of its tile as one pipeline of
+// stages, so that the operands of the next plane load while the current one
+// computes and writes its words.  A launch of many planes over a short k is
+// then not bound by one load latency per plane.
+template <int BM, int BN, int WM, int WN, int FA, int FB>
+__device__ __attribute__((always_inline)) inline void fp4_planes_tile(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P, int s0, int s1,
+    int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
+    constexpr int CH = 4;  // 32-bit chunks per row per 128-bit stage
+    __shared__ Fp4Side<BM, CH, FA, false> sa;
+    __shared__ Fp4Side<BN, CH, FB, true> sb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
+    const int nst = int(K64p / 2);     // stages per plane
+    const int G = (s1 - s0) * nst;     // stages of all planes
+    static_assert(BM % 64 == 0 && NT % 64 == 0, "a wave stages rows of one side only");
+
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    using Stage = uint64_t[RPT][2];
+    auto gload = [&](int g, Stage& dst) {
+        const int64_t s = s0 + g / nst, st = g % nst;
+        const uint64_t* Ap = Apl + s * K64p * Mp + int64_t(tile_m) * BM;
+        const uint64_t* Bp = Bpl + s * K64p * Np + int64_t(tile_n) * BN;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < TL::kRows) {
+                const bool isA = r < BM;
+                const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
+                const int64_t ld = isA ? Mp : Np;
+#pragma unroll
+                for (int w = 0; w < 2; ++w) dst[q][w] = src[(st * 2 + w) * ld];
+            }
+        }
+    };
+    auto store = [&](int buf, const Stage& src) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < TL::kRows) {
+                if (__builtin_amdgcn_readfirstlane(r) < BM) {
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) sa.put(buf, c, r, uint32_t(src[q][c >> 1] >> (32 * (c & 1))));
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        sb.put(buf, c, r - BM, uint32_t(src[q][c >> 1] >> (32 * (c & 1))));
+                }
+            }
+        }
+    };
+    const int g4 = lane >> 4, l16 = lane & 15;
+    auto compute = [&](int buf) {
+        v8i a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = sa.get(buf, g4, wr * WM + 16 * i + l16);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) b[j] = sb.get(buf, g4, wc * WN + 16 * j + l16);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0, 0, 0, 0);
+    };
+
+    Stage sr;
+    gload(0, sr);
+    store(0, sr);
+    __syncthreads();
+    for (int g = 0; g < G; ++g) {
+        const bool more = g + 1 < G;
+        if (more) gload(g + 1, sr);
+        compute(g & 1);
+        products_before_stores(acc);
+        if ((g + 1) % nst == 0) {  // last stage of plane s0 + g / nst
+            fp4_store_parity<BM, BN, WM, WN>(acc, P + int64_t(s0 + g / nst) * Mp * (Np / 64), Np, tile_m, tile_n,
+                                             wr, wc, lane);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+        if (more) store((g & 1) ^ 1, sr);
+        __syncthreads();
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int FA, int FB>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_planes_kernel(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P, int T, int ppw,
+    int64_t Mp, int64_t Np, int64_t K64p)
+{
+    const int s0 = int(blockIdx.z) * ppw, s1 = min(T, s0 + ppw);
+    fp4_planes_tile<BM, BN, WM, WN, FA, FB>(Apl, Bpl, P, s0, s1, Mp, Np, K64p, blockIdx.y, blockIdx.x);
 }
 
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
@@ -577,6 +693,23 @@ hipError_t launch_fp4(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t*
     return hipGetLastError();
 }
 
+template <int BM, int BN, int WM, int WN, int FA, int FB>
+hipError_t launch_fp4_planes(int T, const uint64_t* Apl, const uint64_t* Bpl, uint64_t* P, int64_t m, int64_t n,
+                             int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    const int tm = int(ceil_div(m, BM)), tn = int(ceil_div(n, BN));
+    if (tm * int64_t(BM) > Mp || tn * int64_t(BN) > Np || K64p % 2 || K64p * 64 > kFp4MaxK)
+        return hipErrorInvalidValue;
+    // Planes per workgroup: keep about 4096 workgroups (16 per compute unit)
+    // when there are more (tile, plane) pairs than that.
+    const int ppw = int(std::clamp<int64_t>(int64_t(T) * tm * tn / 4096, 1, T));
+    dim3 grid(tn, tm, unsigned(ceil_div(T, ppw)));
+    hipLaunchKernelGGL((gemm_fp4_planes_kernel<BM, BN, WM, WN, FA, FB>), grid, dim3(TL::kThreads), 0, st, Apl, Bpl,
+                       P, T, ppw, Mp, Np, K64p);
+    return hipGetLastError();
+}
+
 template <class Kern>
 int blocks_filling_device(Kern kernel, int threads)
 {
@@ -665,7 +798,7 @@ GemmShape gemm_shape(int kind)
         case GEMM_MFMA_256x256_W8: return {256, 256};
         case GEMM_FP4_256x256_W8: return {256, 256};
         case GEMM_FP4_128x128: return {128, 128};
-
+        case GEMM_FP4_128x128_PLANES: return {128, 128};
         default: return {0, 0};
     }
 }
@@ -681,7 +814,7 @@ const char* gemm_name(int kind)
         case GEMM_MFMA_256x256_W8: return "mfma_i8_256x256_w8";
         case GEMM_FP4_256x256_W8: return "mfma_fp4_256x256_w8";
         case GEMM_FP4_128x128: return "mfma_fp4_128x128";
-
+        case GEMM_FP4_128x128_PLANES: return "mfma_fp4_128x128_planes";
         default: return "unknown";
     }
 }
@@ -690,7 +823,9 @@ hipError_t launch_gemm(int kind, int T, const uint64_t* Apl, const uint64_t* Bpl
                        int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t K64p, hipStream_t st)
 {
     if (T <= 0 || m <= 0 || n <= 0 || K64p <= 0) return hipSuccess;
-    if (K64p % 4 != 0) return hipErrorInvalidValue;
+    if (kind == GEMM_FP4_128x128_PLANES)
+        return launch_fp4_planes<128, 128, 64, 64, kPacked, kPacked>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);
+    if (K64p % 4 != 0) return hipErrorInvalidValue;  // the other kernels step 256-bit stages
     switch (kind) {
         case GEMM_MFMA_256x256:
             return launch_mfma<256, 256, 128, 128>(T, Apl, Bpl, P, m, n, Mp, Np, K64p, st);

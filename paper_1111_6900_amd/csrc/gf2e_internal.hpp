@@ -11,8 +11,10 @@
 //       base + s*Mp*ldp + i*ldp + w       -- row i, columns [64w, 64w+64), ldp = Np/64
 //
 // Rows are padded to Mp (Np) and the k dimension to K64p words (a multiple of
-// four, so the product kernels step through whole 256-bit stages).  Padding bits are
-// written as zero by the slicing kernels, so padded k contributes nothing.
+// four, so the product kernels step through whole 256-bit stages; products of
+// the plain path with k <= 128 use K64p = 2 and the one kernel with 128-bit
+// stages).  Padding bits are written as zero by the slicing kernels, so padded
+// k contributes nothing.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -37,7 +39,8 @@ enum GemmKind : int {
     GEMM_MFMA_256x256_W8 = 5,  // int8 MFMA, 8 waves of 128x64
     GEMM_FP4_256x256_W8 = 6,   // fp4 MFMA, 8 waves of 128x64 (k < 2^24)
     GEMM_FP4_128x128 = 7,      // fp4 MFMA, 4 waves of 64x64 (k < 2^24)
-    GEMM_NUM_KINDS = 8
+    GEMM_FP4_128x128_PLANES = 8,  // as 7 with 128-bit stages, several planes per workgroup (short k)
+    GEMM_NUM_KINDS = 9
 };
 
 struct GemmShape {

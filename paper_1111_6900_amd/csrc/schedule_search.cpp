@@ -15,8 +15,10 @@
 // gf2e_schedule.hpp, the walk applies random flips, merges whenever
 // possible, and occasionally splits a term in two to leave a plateau.
 //
-// usage: schedule_search e f seconds [seed] [target]
-// prints "rank r" for the best schedule, then its terms "a b c" (decimal).
+// usage: schedule_search e f seconds [seed] [target] [-]
+// With "-" the walk starts from the schedule read from stdin (lines "a b c")
+// instead of Karatsuba.  Prints "rank r" for the best schedule, then its
+// terms "a b c" (decimal).
 #include <chrono>
 #include <cstdint>
 #include <cstdio>
@@ -87,7 +89,7 @@ void simplify(std::vector<Term>& s)
 int main(int argc, char** argv)
 {
     if (argc < 4) {
-        std::fprintf(stderr, "usage: %s e f seconds [seed] [target]\n", argv[0]);
+        std::fprintf(stderr, "usage: %s e f seconds [seed] [target] [-]\n", argv[0]);
         return 2;
     }
     g_e = std::atoi(argv[1]);
@@ -99,14 +101,20 @@ int main(int argc, char** argv)
     const size_t target = argc > 5 ? size_t(std::atoi(argv[5])) : 0;
     if (g_e < 2 || g_e > gf2e::kMaxE) return 2;
 
-    // Start: the Karatsuba schedule with the reduction mod f folded into c.
-    const gf2e::Schedule K = gf2e::build_schedule(g_e);
     std::vector<Term> s;
-    for (int p = 0; p < K.t; ++p) {
-        uint32_t c = 0;
-        for (int d = 0; d < 2 * g_e - 1; ++d)
-            if ((K.w[d] >> p) & 1u) c ^= xpow_mod(d);
-        s.push_back({K.u[p], K.v[p], c});
+    if (argc > 6 && argv[6][0] == '-') {
+        // Start: the schedule on stdin.
+        unsigned a, b, c;
+        while (std::scanf("%u %u %u", &a, &b, &c) == 3) s.push_back({a, b, c});
+    } else {
+        // Start: the Karatsuba schedule with the reduction mod f folded into c.
+        const gf2e::Schedule K = gf2e::build_schedule(g_e);
+        for (int p = 0; p < K.t; ++p) {
+            uint32_t c = 0;
+            for (int d = 0; d < 2 * g_e - 1; ++d)
+                if ((K.w[d] >> p) & 1u) c ^= xpow_mod(d);
+            s.push_back({K.u[p], K.v[p], c});
+        }
     }
     simplify(s);
     if (!is_schedule(s)) return 1;

@@ -38,9 +38,9 @@ struct FieldTabs {
     uint16_t exp[kInLds ? 2 * Q : 1];
     uint16_t log[kInLds ? Q + 1 : 1];
     const uint16_t* gexp;
-    const uint16_t* glog;
+    const uint32_t* glog;
 
-    __device__ void load(const uint16_t* dexp, const uint16_t* dlog)
+    __device__ void load(const uint16_t* dexp, const uint32_t* dlog)
     {
         if constexpr (kInLds) {
             for (int i = threadIdx.x; i < 2 * Q; i += blockDim.x) exp[i] = dexp[i];
@@ -67,7 +67,7 @@ template <int E>
 __global__ __launch_bounds__(kTrsmBlock) void trsm_invert_kernel(const void* __restrict__ Tm, int64_t ldt,
                                                                  int64_t m, int lower, int unit,
                                                                  const uint16_t* __restrict__ dexp,
-                                                                 const uint16_t* __restrict__ dlog,
+                                                                 const uint32_t* __restrict__ dlog,
                                                                  void* __restrict__ Tinv, int* __restrict__ err)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
@@ -132,15 +132,14 @@ bool with_e_host(int e, Fn& fn)
     }
 }
 
-hipError_t launch_trsm_invert(int e, const uint16_t* tabs, int lower, int unit, const void* T, int64_t ldt,
+hipError_t launch_trsm_invert(int e, DevTables tabs, int lower, int unit, const void* T, int64_t ldt,
                               int64_t m, void* Tinv, int* err, hipStream_t s)
 {
     if (m <= 0) return hipSuccess;
-    const uint32_t q = (1u << e) - 1u;
     const dim3 grid(unsigned(ceil_div(m, kTrsmBlock)));
     auto go = [&]<int E>() {
-        hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kTrsmBlock), 0, s, T, ldt, m, lower, unit, tabs,
-                           tabs + 2 * q, Tinv, err);
+        hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kTrsmBlock), 0, s, T, ldt, m, lower, unit, tabs.exp,
+                           tabs.log, Tinv, err);
     };
     if (!with_e_host<2>(e, go)) return hipErrorInvalidValue;
     return hipGetLastError();
@@ -192,8 +191,8 @@ int Ctx::trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32
     if (rc) return rc;
     uint8_t* Tinv = static_cast<uint8_t*>(aux);
     uint8_t* tmp = Tinv + inv_bytes;
-    const uint16_t* tabs = field_tables(e, f);
-    if (!tabs) return GF2E_ENOMEM;
+    const DevTables tabs = field_tables(e, f);
+    if (!tabs.exp) return GF2E_ENOMEM;
     if (launch_trsm_invert(e, tabs, lower, unit, T->data, T->ld, m, Tinv, d_err, s) != hipSuccess) return GF2E_EDEVICE;
 
     const gf2e_mat inv_all{Tinv, nb * kTrsmBlock, kTrsmBlock, kTrsmBlock};

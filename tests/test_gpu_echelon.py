@@ -122,3 +122,22 @@ def test_rref_1024(ctx, e, f, shape, k):
     Eo, ro, po = oracle.echelon(A, e, f)
     assert r == ro and piv == list(po)
     assert (E == Eo).all()
+
+
+@pytest.mark.parametrize("e,f", [(2, 0x7), (8, 0x11D), (12, 0x1053)])
+def test_rref_pivots_beyond_the_first_rows(ctx, e, f):
+    """Pivots that only rows far down can supply: the first rows of a panel
+    lack a pivot in some column (zero there, or linearly dependent), so the
+    pivot search has to look at the remaining rows as well."""
+    gen = np.random.default_rng(4000 + e)
+    A = workload.field_matrix(gen, 700, 130, e)
+    A[:400, 3] = 0
+    A[:400, 70] = 0
+    B = workload.field_matrix(gen, 600, 64, e)
+    B[:300] = B[np.arange(300) % 10]  # rank at most 10 in the first 300 rows
+    for M in (A, B):
+        print(f"rref beyond first rows e={e} shape={M.shape}", flush=True)
+        E, r, piv = gpu_echelon(ctx, M, e, f)
+        Eo, ro, po = oracle.echelon(M, e, f)
+        assert r == ro and piv == list(po)
+        assert (E == Eo).all()

@@ -60,7 +60,7 @@ def test_small_shapes_every_field(ctx, e, f, shape):
     assert (gpu_mul(ctx, A, B, e, f) == oracle.matmul(A, B, e, f)).all()
 
 
-@pytest.mark.parametrize("kind", list(range(8)))
+@pytest.mark.parametrize("kind", list(range(9)))
 @pytest.mark.parametrize("e", [2, 5, 8, 10])
 def test_every_product_kernel(g, e, kind):
     f = workload.DEFAULT_POLY[e]
@@ -93,7 +93,7 @@ def test_alpha_form_small_shapes(actx, e, f, shape):
     assert (gpu_mul(actx, A, B, e, f) == oracle.matmul(A, B, e, f)).all()
 
 
-@pytest.mark.parametrize("kind", list(range(8)))
+@pytest.mark.parametrize("kind", list(range(9)))
 @pytest.mark.parametrize("e", [2, 4, 7])
 def test_alpha_form_every_kernel(g, e, kind):
     f = workload.DEFAULT_POLY[e]
@@ -165,7 +165,7 @@ def test_large_k_parity(ctx, k):
     assert gpu_mul(ctx, A, B, 2, 0x7)[0, 0] == k % 2
 
 
-@pytest.mark.parametrize("kind", [6, 7])
+@pytest.mark.parametrize("kind", [6, 7, 8])
 @pytest.mark.parametrize("k", [2**24 - 64, 2**24 + 1])
 def test_fp4_count_limit(g, kind, k):
     """The fp4 kernels keep exact f32 counts up to 2^24; beyond that the plain
@@ -174,6 +174,29 @@ def test_fp4_count_limit(g, kind, k):
     A = np.ones((1, k), dtype=np.uint8)
     B = np.ones((k, 1), dtype=np.uint8)
     assert gpu_mul(c, A, B, 2, 0x7)[0, 0] == k % 2
+    c.close()
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("e", [3, 8, 13])
+def test_short_k_products(g, e, form):
+    """Products with k <= 128 pad k to 128 bits and run on the kernel with
+    128-bit stages, whatever kernel is forced; the result stays exact for
+    ragged m, n and every k up to 129."""
+    f = {**workload.DEFAULT_POLY, **workload.WIDE_POLY}[e]
+    c = g.Context(0, kernel=g.KERNEL_MFMA_256)
+    c.set_form(form)
+    gen = np.random.default_rng(e * 7 + form)
+    for k in (1, 64, 65, 127, 128, 129):
+        print(f"short k e={e} form={form} k={k}", flush=True)
+        # the alpha form's product has e * K64p words of k: a multiple of 4
+        # words, which every kernel steps, when e is even
+        short = k <= 128 and (form == g.FORM_SCHEDULE or e % 2 == 1)
+        expect = g.KERNEL_FP4_128_PLANES if short else g.KERNEL_MFMA_256
+        assert c.chosen_kernel(e, f, 300, k, 400) == expect
+        A = workload.field_matrix(gen, 300, k, e)
+        B = workload.field_matrix(gen, k, 400, e)
+        assert (gpu_mul(c, A, B, e, f) == oracle.matmul(A, B, e, f)).all()
     c.close()
 
 
