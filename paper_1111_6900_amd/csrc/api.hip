@@ -90,6 +90,10 @@ Plan make_plan(int e, uint32_t f, int64_t m, int64_t k, int64_t n, int form, boo
     p.Mp = round_up(std::max<int64_t>(m, 1), kRowAlign);
     p.Np = round_up(std::max<int64_t>(n, 1), kRowAlign);
     p.K64p = short_k && k <= 128 ? 2 : kwords_padded(std::max<int64_t>(k, 1));
+    // The alpha form's product has e blocks of K64p words along k; with
+    // k <= 64 and e even one word per block keeps that a whole number of
+    // 128-bit stages and halves the product.
+    if (form == kFormAlpha && short_k && k <= 64 && e % 2 == 0) p.K64p = 1;
     if (form == kFormAlpha) {
         p.sid = kIdentitySchedule;
         p.T = e;
@@ -559,6 +563,7 @@ void gf2e_destroy(gf2e_ctx* handle)
     if (c->ws) (void)hipFree(c->ws);
     if (c->aux) (void)hipFree(c->aux);
     for (auto& kv : c->ftabs) (void)hipFree(kv.second);
+    if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->d_err) (void)hipFree(c->d_err);
     for (int st = 0; st < GF2E_NUM_STAGES; ++st)
         for (auto& pr : c->prof_pending[st]) {

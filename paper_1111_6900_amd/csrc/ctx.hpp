@@ -128,6 +128,11 @@ struct Ctx {
     // and log[q + 1] (uint32, log 0 = 2q), so that exp[log a + log b] = a*b.
     std::map<uint64_t, void*> ftabs;
     DevTables field_tables(int e, uint32_t f);  // {nullptr, nullptr} on failure
+    // Pinned host buffer for small device-to-host reads (the pivot state of
+    // an echelon panel), so that they are truly asynchronous.
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    void* ensure_pinned(size_t bytes);
     // Row echelon form in place (reduced when full); host-synchronous.
     int echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s);
     void release_batches();

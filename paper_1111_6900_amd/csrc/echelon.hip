@@ -51,8 +51,6 @@ struct DevField {
 constexpr int kMaxLdsQ = 1023;  // tables staged in LDS up to e = 10
 constexpr int kLdsExp = 4 * kMaxLdsQ + 1;
 
-__device__ inline uint32_t fmul(const DevField& F, uint32_t a, uint32_t b) { return F.exp[F.log[a] + F.log[b]]; }
-__device__ inline uint32_t finv(const DevField& F, uint32_t a) { return F.exp[F.q - F.log[a]]; }
 
 __device__ inline uint32_t ld_el(const void* M, int wide, int64_t i)
 {
@@ -209,70 +207,102 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
 }
 
 // W = K^{-1}, K[s][t] = orig[r + rows[s]][cols[t]] (rp x rp), by Gauss-Jordan
-// on [K | I] in LDS; W is written as elements, row pitch rp.  Thread
-// (ty, tx) of the 8 x 128 block handles column tx of rows ty, ty + 8, ...
-// Step t leaves column t of K alone: it is never read again, and since no
-// thread writes it, the multipliers M[s][t] can be read while other
-// columns are updated.
+// on [K | I] without row exchanges: step t takes as pivot the first row not
+// yet used with a nonzero entry in column t, scales it to 1 there and clears
+// column t from every other row; the row that pivoted on column t ends as
+// row t of [I | K^{-1}].  W is written as elements, row pitch rp.
+// Thread (ty, tx) of the 8 x 128 block keeps column tx of rows 8ty..8ty+7
+// in registers.  Per step only column t (as logarithms) and the scaled
+// pivot row pass through LDS, double-buffered; every wave picks the pivot
+// itself from column t, so a step costs two barriers and no row is moved.
 constexpr int kInvThreads = 1024;
 
 template <bool LDS_TABS>
 __global__ __launch_bounds__(kInvThreads) void pivot_inverse_kernel(const uint16_t* orig, int64_t r,
                                                                     const PanelState* st, int wide, void* W,
-                                                                    DevField Fg)
+                                                                    DevField F)
 {
     constexpr int kCols = 2 * kPanel, kRowGroups = kInvThreads / kCols, RPT = kPanel / kRowGroups;
-    __shared__ uint16_t M[kPanel][kCols + 1];
     __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
     __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
-    __shared__ int prow;
-    __shared__ uint32_t pinv;
+    __shared__ __align__(16) uint32_t lcol[2][kPanel];  // logs of column t (2q for zeros)
+    __shared__ uint16_t prow[2][kCols];   // the scaled pivot row
+    __shared__ int pivot_of[kPanel];      // row that pivoted on column t
+    __shared__ int row_pos[kPanel];       // its inverse
     const int rp = st->rp;
+    const int q = int(F.q);
     const int tid = threadIdx.x, tx = tid % kCols, ty = tid / kCols;
     if constexpr (LDS_TABS) {  // tables in LDS when they fit (e <= 10)
-        for (int k = tid; k <= int(4 * Fg.q); k += kInvThreads) sexp[k] = Fg.exp[k];
-        for (int k = tid; k <= int(Fg.q); k += kInvThreads) slog[k] = Fg.log[k];
+        for (int k = tid; k <= 4 * q; k += kInvThreads) sexp[k] = F.exp[k];
+        for (int k = tid; k <= q; k += kInvThreads) slog[k] = F.log[k];
     }
-    const DevField F = LDS_TABS ? DevField{sexp, slog, Fg.q} : Fg;
-    if (tx < 2 * rp)
-        for (int s = ty; s < kPanel; s += kRowGroups)  // rows rp.. stay zero
-            M[s][tx] = s >= rp ? uint16_t(0)
-                       : tx < rp ? orig[(r + st->rows[s]) * kPanel + st->cols[tx]]
-                                 : uint16_t(tx - rp == s ? 1 : 0);
+    const uint16_t* ex = LDS_TABS ? sexp : F.exp;
+    const uint32_t* lg = LDS_TABS ? slog : F.log;
+    uint32_t v[RPT];  // v[k] = M[RPT * ty + k][tx]; zero outside the rp x 2rp matrix
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int s = RPT * ty + k;
+        v[k] = s >= rp || tx >= 2 * rp ? 0u
+               : tx < rp              ? uint32_t(orig[(r + st->rows[s]) * kPanel + st->cols[tx]])
+                                      : uint32_t(tx - rp == s ? 1 : 0);
+    }
+    bool used = false;  // lane s of every wave tracks row s
+    const int lane = tid & 63;
     __syncthreads();
     for (int t = 0; t < rp; ++t) {
-        if (tid < 64) {  // pivot: the first row s >= t with M[s][t] != 0 (K is invertible)
-            const uint64_t bal = __ballot(tid >= t && tid < rp && M[tid][t] != 0);
-            if (tid == 0) {
-                const int p = bal ? __ffsll(static_cast<long long>(bal)) - 1 : t;
-                prow = p;
-                pinv = bal ? finv(F, M[p][t]) : 0u;
-            }
-        }
-        __syncthreads();
-        const int p = prow;
-        // swap rows p and t, then scale row t so that its entry t is 1
-        if (ty == 0 && tx < 2 * rp) {
-            const uint16_t a = M[p][tx], b = M[t][tx];
-            M[p][tx] = b;
-            M[t][tx] = uint16_t(fmul(F, pinv, a));
-        }
-        __syncthreads();
-        // eliminate column t from the other rows (zero entries give a zero
-        // product through log 0 = 2q, so there is no branch per row)
-        if (tx < 2 * rp && tx != t) {
-            const int lp = int(F.log[M[t][tx]]);
+        const int b = t & 1;
+        if (tx == t) {
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const int s = ty + k * kRowGroups;
-                const uint32_t x = s == t ? 0u : M[s][t];  // rows s >= rp hold zeros
-                M[s][tx] ^= F.exp[int(F.log[x]) + lp];
-            }
+            for (int k = 0; k < RPT; ++k) lcol[b][RPT * ty + k] = lg[v[k]];
         }
         __syncthreads();
+        // Every wave finds the same pivot: the first unused row with a
+        // nonzero entry in column t (K is invertible, so one exists).
+        const uint32_t lc = lcol[b][lane];
+        const uint64_t bal = __ballot(!used && lane < rp && lc != uint32_t(2 * q));
+        const int p = bal ? __ffsll(static_cast<long long>(bal)) - 1 : t;
+        used |= lane == p;
+        if (tid == 0) pivot_of[t] = p;
+        if (ty == p / RPT) {  // the pivot row's owners scale it and publish it
+            const int plinv = bal ? q - int(lcol[b][p]) : 2 * q;  // log of 1 / M[p][t]
+            const int kp = p % RPT;
+            uint32_t x = 0;
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) x = k == kp ? v[k] : x;
+            const uint32_t y = ex[plinv + int(lg[x])];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) v[k] = k == kp ? y : v[k];
+            prow[b][tx] = uint16_t(y);
+        }
+        __syncthreads();
+        // M[s][tx] += M[s][t] * (pivot row)[tx] for s != p: the multipliers'
+        // logs are one contiguous run of lcol, all lookups independent
+        const int lp = int(lg[prow[b][tx]]);
+        uint32_t ls[RPT];
+        const uint4* lv = reinterpret_cast<const uint4*>(&lcol[b][RPT * ty]);
+#pragma unroll
+        for (int h = 0; h < RPT / 4; ++h) {
+            const uint4 w = lv[h];
+            ls[4 * h] = w.x;
+            ls[4 * h + 1] = w.y;
+            ls[4 * h + 2] = w.z;
+            ls[4 * h + 3] = w.w;
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const uint32_t l = RPT * ty + k == p ? uint32_t(2 * q) : ls[k];
+            v[k] ^= ex[int(l) + lp];
+        }
     }
-    if (tx < rp)
-        for (int s = ty; s < rp; s += kRowGroups) st_el(W, wide, int64_t(s) * rp + tx, M[s][rp + tx]);
+    if (tid < rp) row_pos[pivot_of[tid]] = tid;
+    __syncthreads();
+    if (tx >= rp && tx < 2 * rp) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int s = RPT * ty + k;
+            if (s < rp) st_el(W, wide, int64_t(row_pos[s]) * rp + (tx - rp), v[k]);
+        }
+    }
 }
 
 // G[i][t] = original entry of (new) row i at pivot column t, for all rows:
@@ -360,6 +390,21 @@ DevTables Ctx::field_tables(int e, uint32_t f)
     return view(d);
 }
 
+void* Ctx::ensure_pinned(size_t bytes)
+{
+    if (pinned_bytes >= bytes) return pinned;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_bytes = 0;
+    if (hipHostMalloc(&pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        pinned = nullptr;
+        return nullptr;
+    }
+    pinned_bytes = bytes;
+    return pinned;
+}
+
 int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s)
 {
     const int64_t m = A->rows, n = A->cols;
@@ -405,7 +450,16 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     uint8_t* x1 = G + b_g;
     uint8_t* mvbuf = x1 + b_x1;
 
-    PanelState hs;
+    PanelState* hsp = static_cast<PanelState*>(ensure_pinned(sizeof(PanelState)));
+    if (!hsp) return GF2E_ENOMEM;
+    hipEvent_t sel_done = get_event();
+    if (!sel_done) return GF2E_EDEVICE;
+    struct EventBack {  // back to the pool on every return
+        Ctx* c;
+        hipEvent_t ev;
+        ~EventBack() { c->event_pool.push_back(ev); }
+    } event_back{this, sel_done};
+    const PanelState& hs = *hsp;
     std::vector<int> hperm;
     std::vector<char> is_piv;
     uint8_t* Ad = static_cast<uint8_t*>(A->data);
@@ -429,11 +483,23 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         // Probe on the first rows; the whole tournament only when they lack a
         // pivot in some column and further rows exist.
         const int64_t probe = std::min<int64_t>(mr, kProbeRows);
+        auto launch_inverse = [&] {
+            if (lds_tabs)
+                hipLaunchKernelGGL(pivot_inverse_kernel<true>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide, W,
+                                   F);
+            else
+                hipLaunchKernelGGL(pivot_inverse_kernel<false>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide,
+                                   W, F);
+        };
         launch_select.template operator()<kProbeRows>(1, probe, static_cast<const int*>(nullptr), cand[0], 1);
-        if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-        if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+        // The state goes to the host while the device already inverts the
+        // probe's pivot block (redone below if the tournament runs).
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(hsp, st, sizeof(PanelState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(sel_done, s) != hipSuccess)
             return GF2E_EDEVICE;
+        launch_inverse();
+        if (hipEventSynchronize(sel_done) != hipSuccess) return GF2E_EDEVICE;
         if (hs.rp < bc && mr > probe) {
             // Tournament levels until one workgroup holds all candidates.
             const int* in = nullptr;
@@ -447,9 +513,10 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                 ncand = nb * kPanel;
             }
             if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-            if (hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            if (hipMemcpyAsync(hsp, st, sizeof(PanelState), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return GF2E_EDEVICE;
+            launch_inverse();
         }
         const int rp = hs.rp;
         if (rp == 0) continue;
@@ -481,10 +548,6 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         if (hipMemcpyAsync(perm, hperm.data(), size_t(mr + nm) * 4, hipMemcpyHostToDevice, s) != hipSuccess)
             return GF2E_EDEVICE;
 
-        if (lds_tabs)
-            hipLaunchKernelGGL(pivot_inverse_kernel<true>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide, W, F);
-        else
-            hipLaunchKernelGGL(pivot_inverse_kernel<false>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide, W, F);
         hipLaunchKernelGGL(gather_pivot_columns_kernel, dim3(unsigned(ceil_div(m * rp, 256))), dim3(256), 0, s, orig,
                            r, m, perm, st, rp, wide, G);
         const int64_t nc = n - c0;

@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void slice_rows_kernel(
     const void* __restrict__ A, int64_t lda, int64_t m, int64_t k, uint64_t* __restrict__ planes,
     int64_t Mp, int64_t K64p, int* __restrict__ err)
 {
-    const int64_t r = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= Mp) return;
     slice_row_word<E, SID>(A, lda, m, k, planes, Mp, K64p, err, r, blockIdx.y);
 }
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void slice_cols_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
-    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= Np) return;
     slice_col_word<E, SID>(B, ldb, k, n, planes, Np, K64p, err, j, blockIdx.y);
 }
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void slice_cols_alpha_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint32_t f, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
-    const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= Np) return;
     slice_col_word_alpha<E>(B, ldb, k, n, f, planes, Np, K64p, err, j, blockIdx.y);
 }
@@ -449,13 +449,19 @@ __global__ void zero_kernel(uint8_t* C, int64_t rows, int64_t row_bytes, int64_t
 
 }  // namespace
 
+// Threads per block of a slicing launch over `words` plane words (one per
+// thread): small launches take 64-thread blocks, so that their work spreads
+// over more compute units.
+static unsigned slice_block(int64_t words) { return words < 256 * 1024 ? 64u : unsigned(kThreads); }
+
 hipError_t launch_slice_rows(int e, int sid, const void* A, int64_t lda, int64_t m, int64_t k,
                              uint64_t* planes, int64_t Mp, int64_t K64p, int* err, hipStream_t s)
 {
     if (Mp <= 0 || K64p <= 0) return hipSuccess;
-    dim3 grid(unsigned(ceil_div(Mp, kThreads)), unsigned(K64p));
+    const unsigned bs = slice_block(Mp * K64p);
+    dim3 grid(unsigned(ceil_div(Mp, bs)), unsigned(K64p));
     if (!with_any_schedule(e, sid, [&]<int E, int SID>() {
-            hipLaunchKernelGGL((slice_rows_kernel<E, SID>), grid, dim3(kThreads), 0, s, A, lda, m, k, planes,
+            hipLaunchKernelGGL((slice_rows_kernel<E, SID>), grid, dim3(bs), 0, s, A, lda, m, k, planes,
                                Mp, K64p, err);
         }))
         return hipErrorInvalidValue;
@@ -466,9 +472,10 @@ hipError_t launch_slice_cols(int e, int sid, const void* B, int64_t ldb, int64_t
                              uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s)
 {
     if (Np <= 0 || K64p <= 0) return hipSuccess;
-    dim3 grid(unsigned(ceil_div(Np, kThreads)), unsigned(K64p));
+    const unsigned bs = slice_block(Np * K64p);
+    dim3 grid(unsigned(ceil_div(Np, bs)), unsigned(K64p));
     if (!with_schedule(e, sid, [&]<int E, int SID>() {
-            hipLaunchKernelGGL((slice_cols_kernel<E, SID>), grid, dim3(kThreads), 0, s, B, ldb, k, n, planes,
+            hipLaunchKernelGGL((slice_cols_kernel<E, SID>), grid, dim3(bs), 0, s, B, ldb, k, n, planes,
                                Np, K64p, err);
         }))
         return hipErrorInvalidValue;
@@ -479,9 +486,10 @@ hipError_t launch_slice_cols_alpha(int e, uint32_t f, const void* B, int64_t ldb
                                    uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s)
 {
     if (Np <= 0 || K64p <= 0) return hipSuccess;
-    dim3 grid(unsigned(ceil_div(Np, kThreads)), unsigned(K64p));
+    const unsigned bs = slice_block(Np * K64p);
+    dim3 grid(unsigned(ceil_div(Np, bs)), unsigned(K64p));
     if (!with_e(e, [&]<int E>() {
-            hipLaunchKernelGGL((slice_cols_alpha_kernel<E>), grid, dim3(kThreads), 0, s, B, ldb, k, n, f,
+            hipLaunchKernelGGL((slice_cols_alpha_kernel<E>), grid, dim3(bs), 0, s, B, ldb, k, n, f,
                                planes, Np, K64p, err);
         }))
         return hipErrorInvalidValue;
