@@ -138,6 +138,55 @@ __device__ __attribute__((always_inline)) inline void load_col_planes(const void
     bytes_to_planes<E>(lo, hi, pl);
 }
 
+// Bit-planes of one column word for a block of 64 columns (one wave per
+// block): the 64 x 64 tile of B (k-bits [64kw, 64kw+64), columns
+// j0..j0+63) is read with 16-byte row pieces where they are aligned, staged
+// in LDS row-major, and each lane then reads its own column from LDS.  That
+// replaces 64 narrow global loads per lane by a few wide ones.
+template <int E>
+__device__ __attribute__((always_inline)) inline void load_col_planes_tile(const void* __restrict__ B, int64_t ldb,
+                                                                            int64_t k, int64_t n,
+                                                                            int* __restrict__ err, int64_t j0,
+                                                                            int64_t kw, int lane, uint64_t (&pl)[E])
+{
+    using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
+    constexpr int EB = int(sizeof(elem_t)), RB = 64 * EB, CH = RB / 16, PE = 16 / EB;
+    __shared__ __align__(16) uint8_t tile[64][RB + 16];
+    const elem_t* base = static_cast<const elem_t*>(B);
+    const int64_t r0 = kw * 64;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        const int q = lane + 64 * i, row = q / CH, pc = q % CH;
+        const int64_t gr = r0 + row, gc = j0 + int64_t(pc) * PE;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gr < k && gc < n) {
+            const elem_t* src = base + gr * ldb + gc;
+            if (gc + PE <= n && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+                v = *reinterpret_cast<const uint4*>(src);
+            } else {
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < PE; ++e)
+                    if (gc + e < n) w[e * EB / 4] |= uint32_t(src[e]) << (8 * ((e * EB) % 4));
+                v = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+        *reinterpret_cast<uint4*>(&tile[row][pc * 16]) = v;
+    }
+    __syncthreads();
+    uint64_t lo[8] = {}, hi[8] = {};
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 64; ++c) {
+        const uint32_t x = reinterpret_cast<const elem_t*>(tile[c])[lane];
+        bad |= (x >> E) != 0;
+        lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
+        if constexpr (E > 8) hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));
+    }
+    if (bad) atomicOr(err, 1);
+    bytes_to_planes<E>(lo, hi, pl);
+}
+
 // Column slicing of one plane word into the schedule's B-side operands.
 template <int E, int SID>
 __device__ __attribute__((always_inline)) inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
@@ -156,15 +205,13 @@ __device__ __attribute__((always_inline)) inline void slice_col_word(const void*
 // is folded into that matrix.  Block (i, c), word (kw, j) is stored at
 // planes[(i*K64p + kw)*E*Np + c*Np + j].  alpha^(i+1) B = x * alpha^i B on
 // bit-planes: shift up by one and fold the plane that leaves back in with f.
+// This writes the blocks (i, c) of column j, k-word kw, from the bit-planes
+// cur of B (cur is consumed).
 template <int E>
-__device__ __attribute__((always_inline)) inline void slice_col_word_alpha(const void* __restrict__ B, int64_t ldb,
-                                                                            int64_t k, int64_t n, uint32_t f,
-                                                                            uint64_t* __restrict__ planes, int64_t Np,
-                                                                            int64_t K64p, int* __restrict__ err,
-                                                                            int64_t j, int64_t kw)
+__device__ __attribute__((always_inline)) inline void store_alpha_blocks(uint64_t (&cur)[E], uint32_t f,
+                                                                          uint64_t* __restrict__ planes, int64_t Np,
+                                                                          int64_t K64p, int64_t j, int64_t kw)
 {
-    uint64_t cur[E];
-    load_col_planes<E>(B, ldb, k, n, err, j, kw, cur);
     uint64_t fm[E];
 #pragma unroll
     for (int b = 0; b < E; ++b) fm[b] = 0ull - uint64_t((f >> b) & 1u);
@@ -284,24 +331,29 @@ __global__ __launch_bounds__(kThreads) void slice_rows_kernel(
     slice_row_word<E, SID>(A, lda, m, k, planes, Mp, K64p, err, r, blockIdx.y);
 }
 
+// Column slicing: one wave per block of 64 columns and one k-word.
+constexpr int kColBlock = 64;
+
 template <int E, int SID>
-__global__ __launch_bounds__(kThreads) void slice_cols_kernel(
+__global__ __launch_bounds__(kColBlock) void slice_cols_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= Np) return;
-    slice_col_word<E, SID>(B, ldb, k, n, planes, Np, K64p, err, j, blockIdx.y);
+    const int64_t j0 = int64_t(blockIdx.x) * kColBlock, kw = blockIdx.y;
+    uint64_t pl[E];
+    load_col_planes_tile<E>(B, ldb, k, n, err, j0, kw, threadIdx.x, pl);
+    store_operands<E, SID, true>(pl, planes + kw * Np + j0 + threadIdx.x, K64p * Np);
 }
 
 template <int E>
-__global__ __launch_bounds__(kThreads) void slice_cols_alpha_kernel(
+__global__ __launch_bounds__(kColBlock) void slice_cols_alpha_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint32_t f, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= Np) return;
-    slice_col_word_alpha<E>(B, ldb, k, n, f, planes, Np, K64p, err, j, blockIdx.y);
+    const int64_t j0 = int64_t(blockIdx.x) * kColBlock, kw = blockIdx.y;
+    uint64_t cur[E];
+    load_col_planes_tile<E>(B, ldb, k, n, err, j0, kw, threadIdx.x, cur);
+    store_alpha_blocks<E>(cur, f, planes, Np, K64p, j0 + threadIdx.x, kw);
 }
 
 template <int E, int SID>
@@ -472,10 +524,9 @@ hipError_t launch_slice_cols(int e, int sid, const void* B, int64_t ldb, int64_t
                              uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s)
 {
     if (Np <= 0 || K64p <= 0) return hipSuccess;
-    const unsigned bs = slice_block(Np * K64p);
-    dim3 grid(unsigned(ceil_div(Np, bs)), unsigned(K64p));
+    dim3 grid(unsigned(ceil_div(Np, kColBlock)), unsigned(K64p));
     if (!with_schedule(e, sid, [&]<int E, int SID>() {
-            hipLaunchKernelGGL((slice_cols_kernel<E, SID>), grid, dim3(bs), 0, s, B, ldb, k, n, planes,
+            hipLaunchKernelGGL((slice_cols_kernel<E, SID>), grid, dim3(kColBlock), 0, s, B, ldb, k, n, planes,
                                Np, K64p, err);
         }))
         return hipErrorInvalidValue;
@@ -486,10 +537,9 @@ hipError_t launch_slice_cols_alpha(int e, uint32_t f, const void* B, int64_t ldb
                                    uint64_t* planes, int64_t Np, int64_t K64p, int* err, hipStream_t s)
 {
     if (Np <= 0 || K64p <= 0) return hipSuccess;
-    const unsigned bs = slice_block(Np * K64p);
-    dim3 grid(unsigned(ceil_div(Np, bs)), unsigned(K64p));
+    dim3 grid(unsigned(ceil_div(Np, kColBlock)), unsigned(K64p));
     if (!with_e(e, [&]<int E>() {
-            hipLaunchKernelGGL((slice_cols_alpha_kernel<E>), grid, dim3(bs), 0, s, B, ldb, k, n, f,
+            hipLaunchKernelGGL((slice_cols_alpha_kernel<E>), grid, dim3(kColBlock), 0, s, B, ldb, k, n, f,
                                planes, Np, K64p, err);
         }))
         return hipErrorInvalidValue;

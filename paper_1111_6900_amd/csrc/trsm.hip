@@ -4,8 +4,9 @@
 // The paper's algorithm walks the rows one by one and updates the rows above
 // with Newton-John tables.  Here the solve is blocked for the GPU:
 //   1. one kernel inverts all 128 x 128 diagonal blocks of T at once (one
-//      workgroup per block, one thread per column of the inverse, field
-//      products by log/antilog tables, in LDS for e <= 10);
+//      workgroup of 1024 threads per block, right-looking substitution with
+//      the block in registers, field products by log/antilog tables, in LDS
+//      for e <= 10);
 //   2. a recursion over block ranges turns the rest into products on the
 //      bitsliced path: for upper T,
 //          X2 = solve(T22, B2);  B1 += T12 * X2;  X1 = solve(T11, B1),
@@ -28,94 +29,100 @@ namespace {
 
 constexpr int kTrsmBlock = 128;  // diagonal block size = threads per workgroup
 
-// Log/antilog tables of F_{2^E} (exp[i] = g^i for i < 2q, q = 2^E - 1; log
-// the inverse map on nonzero elements), staged in LDS for E <= 10 and read
-// from the device copy otherwise.
-template <int E>
-struct FieldTabs {
-    static constexpr int Q = (1 << E) - 1;
-    static constexpr bool kInLds = E <= 10;
-    uint16_t exp[kInLds ? 2 * Q : 1];
-    uint16_t log[kInLds ? Q + 1 : 1];
-    const uint16_t* gexp;
-    const uint32_t* glog;
-
-    __device__ void load(const uint16_t* dexp, const uint32_t* dlog)
-    {
-        if constexpr (kInLds) {
-            for (int i = threadIdx.x; i < 2 * Q; i += blockDim.x) exp[i] = dexp[i];
-            for (int i = threadIdx.x; i <= Q; i += blockDim.x) log[i] = dlog[i];
-        }
-        if (threadIdx.x == 0) {
-            gexp = dexp;
-            glog = dlog;
-        }
-        __syncthreads();
-    }
-    __device__ uint32_t ex(int i) const { return kInLds ? exp[i] : gexp[i]; }
-    __device__ uint32_t lg(uint32_t a) const { return kInLds ? log[a] : glog[a]; }
-    __device__ uint32_t mul(uint32_t a, uint32_t b) const { return (a && b) ? ex(lg(a) + lg(b)) : 0u; }
-    __device__ uint32_t inv(uint32_t a) const { return ex(Q - lg(a)); }  // a != 0
-};
-
 // Inverse of diagonal block q of T (rows and columns [128q, 128q + bs)),
-// written row-major with leading dimension 128 at Tinv + 128q*128.  Thread c
-// computes column c of the inverse by substitution on T_qq x = e_c.  Only
-// the triangle of T is read; unit = 1 takes the diagonal as ones.  Flags:
-// err |= 1 for an entry >= 2^E, err |= 2 for a zero on the diagonal.
+// written row-major with leading dimension 128 at Tinv + 128q*128 (columns
+// < bs).  Right-looking substitution on T_qq X = I: step i (i ascending for
+// lower T, descending for upper) finishes row i of X as R_i / T_ii, then
+// every row j still to come takes R_j -= T_ji X_i.  Thread (ty, c) of the
+// 8 x 128 block keeps column c of R for rows ty, ty + 8, ... in registers;
+// per step the new row of X passes through LDS (as logarithms, double-
+// buffered), so a step costs one barrier and 16 independent table lookups per
+// thread.  The triangle of T is staged once as logarithms.  Field products
+// use the device tables (exp with a zero tail, log 0 = 2q), in LDS for
+// e <= 10.  Only the triangle of T is read; unit = 1 takes the diagonal as
+// ones.  Flags: err |= 1 for an entry >= 2^E, err |= 2 for a zero on the
+// diagonal.
+constexpr int kInvGroups = 8;  // threads per column
+constexpr int kInvThreads = kTrsmBlock * kInvGroups;
+
 template <int E>
-__global__ __launch_bounds__(kTrsmBlock) void trsm_invert_kernel(const void* __restrict__ Tm, int64_t ldt,
-                                                                 int64_t m, int lower, int unit,
-                                                                 const uint16_t* __restrict__ dexp,
-                                                                 const uint32_t* __restrict__ dlog,
-                                                                 void* __restrict__ Tinv, int* __restrict__ err)
+__global__ __launch_bounds__(kInvThreads) void trsm_invert_kernel(const void* __restrict__ Tm, int64_t ldt,
+                                                                  int64_t m, int lower, int unit,
+                                                                  const uint16_t* __restrict__ dexp,
+                                                                  const uint32_t* __restrict__ dlog,
+                                                                  void* __restrict__ Tinv, int* __restrict__ err)
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
-    __shared__ FieldTabs<E> tabs;
-    __shared__ uint16_t Ts[kTrsmBlock][kTrsmBlock + 1];
-    __shared__ uint16_t Xs[kTrsmBlock][kTrsmBlock + 1];
-    tabs.load(dexp, dlog);
+    constexpr int Q = (1 << E) - 1, RPT = kTrsmBlock / kInvGroups;
+    constexpr bool kLds = E <= 10;
+    __shared__ uint16_t sexp[kLds ? 4 * Q + 1 : 1];
+    __shared__ uint32_t slog[kLds ? Q + 1 : 1];
+    __shared__ uint32_t LT[kTrsmBlock][kTrsmBlock + 1];  // log T[i][l] (2q for zeros and outside)
+    __shared__ uint32_t dlinv[kTrsmBlock];               // log of 1 / T[i][i] (0 for a unit diagonal)
+    __shared__ uint32_t xlog[2][kTrsmBlock];             // log X[i][c] of the newest row
+    const int tid = threadIdx.x, c = tid % kTrsmBlock, ty = tid / kTrsmBlock;
+    if constexpr (kLds) {
+        for (int k = tid; k <= 4 * Q; k += kInvThreads) sexp[k] = dexp[k];
+        for (int k = tid; k <= Q; k += kInvThreads) slog[k] = dlog[k];
+        __syncthreads();
+    }
+    const uint16_t* ex = kLds ? sexp : dexp;
+    const uint32_t* lg = kLds ? slog : dlog;
 
     const int64_t r0 = int64_t(blockIdx.x) * kTrsmBlock;
     const int bs = int(m - r0 < kTrsmBlock ? m - r0 : kTrsmBlock);
     const elem_t* T = static_cast<const elem_t*>(Tm);
-    const int c = threadIdx.x;
     bool bad = false;
-    for (int i = 0; i < bs; ++i) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int i = ty + kInvGroups * k;
         uint32_t v = 0;
-        const bool inside = c < bs && (lower ? c <= i : c >= i);
-        if (inside && !(unit && c == i)) {
+        if (i < bs && c < bs && (lower ? c < i : c > i)) {  // the strict triangle
             v = T[(r0 + i) * ldt + r0 + c];
             bad |= (v >> E) != 0;
-            v &= (1u << E) - 1u;
+            v &= uint32_t(Q);
         }
-        Ts[i][c] = uint16_t(v);
+        LT[i][c] = lg[v];
     }
-    __syncthreads();
+    if (ty == 0) {
+        uint32_t d = 1;
+        if (!unit && c < bs) {
+            d = T[(r0 + c) * ldt + r0 + c];
+            bad |= (d >> E) != 0;
+            d &= uint32_t(Q);
+            if (d == 0) atomicOr(err, 2);
+        }
+        const uint32_t ld = lg[d];
+        dlinv[c] = d ? (uint32_t(Q) - ld) % uint32_t(Q) : uint32_t(2 * Q);
+    }
     if (bad) atomicOr(err, 1);
-    if (!unit && c < bs && Ts[c][c] == 0) atomicOr(err, 2);
+    __syncthreads();
 
-    if (c < bs) {
-        for (int step = 0; step < bs; ++step) {
-            const int i = lower ? step : bs - 1 - step;
-            uint32_t x = 0;
-            if (lower ? i >= c : i <= c) {
-                uint32_t acc = i == c ? 1u : 0u;
-                if (lower) {
-                    for (int l = c; l < i; ++l) acc ^= tabs.mul(Ts[i][l], Xs[l][c]);
-                } else {
-                    for (int l = i + 1; l <= c; ++l) acc ^= tabs.mul(Ts[i][l], Xs[l][c]);
-                }
-                const uint32_t d = Ts[i][i];
-                x = unit ? acc : (d ? tabs.mul(tabs.inv(d), acc) : 0u);
-            }
-            Xs[i][c] = uint16_t(x);
+    uint32_t R[RPT];  // R[k]: column c of row ty + 8k, initially the identity
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) R[k] = ty + kInvGroups * k == c ? 1u : 0u;
+    elem_t* out = static_cast<elem_t*>(Tinv) + r0 * kTrsmBlock;
+    for (int step = 0; step < bs; ++step) {
+        const int i = lower ? step : bs - 1 - step;
+        const int b = step & 1;
+        if (ty == i % kInvGroups) {  // row i is final: X[i][c] = R_i / T_ii
+            const int ki = i / kInvGroups;
+            uint32_t r = 0;
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) r = k == ki ? R[k] : r;
+            const uint32_t x = ex[lg[r] + dlinv[i]];
+            if (c < bs) out[int64_t(i) * kTrsmBlock + c] = elem_t(x);
+            xlog[b][c] = lg[x];
+        }
+        __syncthreads();
+        const uint32_t lx = xlog[b][c];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int j = ty + kInvGroups * k;
+            const uint32_t d = ex[LT[j][i] + lx];
+            R[k] = (lower ? j > i : j < i) ? R[k] ^ d : R[k];
         }
     }
-    __syncthreads();
-    elem_t* out = static_cast<elem_t*>(Tinv);
-    if (c < bs)
-        for (int i = 0; i < bs; ++i) out[(r0 + i) * kTrsmBlock + c] = elem_t(Xs[i][c]);
 }
 
 template <int E, class Fn>
@@ -138,7 +145,7 @@ hipError_t launch_trsm_invert(int e, DevTables tabs, int lower, int unit, const 
     if (m <= 0) return hipSuccess;
     const dim3 grid(unsigned(ceil_div(m, kTrsmBlock)));
     auto go = [&]<int E>() {
-        hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kTrsmBlock), 0, s, T, ldt, m, lower, unit, tabs.exp,
+        hipLaunchKernelGGL((trsm_invert_kernel<E>), grid, dim3(kInvThreads), 0, s, T, ldt, m, lower, unit, tabs.exp,
                            tabs.log, Tinv, err);
     };
     if (!with_e_host<2>(e, go)) return hipErrorInvalidValue;
