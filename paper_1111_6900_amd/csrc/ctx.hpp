@@ -109,15 +109,17 @@ struct Ctx {
     int tune_now(int e, uint32_t f, int64_t m, int64_t k, int64_t n, hipStream_t s);
     void load_tune_cache();
     void save_tune_entry(uint64_t key, int choice);
-    // C = A*B, or C += A*B with acc (shapes already validated).
+    // C = A*B, or C += A*B with acc (shapes already validated).  C may
+    // overlap B: B is sliced into its planes before the last kernel writes
+    // C, all in stream order (the library's own callers use that).
     int mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, hipStream_t s,
             bool acc = false);
     // Launches the stages of plan p with product kernel kind; planes in ws.
     int exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const void* B, int64_t ldb,
                   void* C, int64_t ldc, hipStream_t s, bool acc = false);
 
-    // Buffers of the triangular solver (inverted diagonal blocks, one
-    // block row of results), kept apart from the product workspace.
+    // Buffers of the triangular solver (inverted diagonal blocks) and of
+    // the echelon driver, kept apart from the product workspace.
     void* aux = nullptr;
     int64_t aux_bytes = 0;
     int ensure_aux(int64_t bytes, hipStream_t s);

@@ -431,14 +431,14 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     }
 
     // Buffers: the panel copy, two candidate lists of the tournament, panel
-    // state, permutation and row moves, W, pivot-column gather, the reduced
-    // pivot rows X1, and the moved rows of one panel.
+    // state, permutation and row moves, W, pivot-column gather, and the
+    // moved rows of one panel.
     auto al = [](int64_t b) { return round_up(b, 256); };
     const int64_t b_orig = al(m * kPanel * 2), b_cand = al(ceil_div(m, kSelRows) * kPanel * 4),
                   b_state = al(sizeof(PanelState)), b_perm = al((m + 2 * kPanel) * 4),
-                  b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz), b_x1 = al(kPanel * n * esz),
+                  b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz),
                   b_mv = al(2 * kPanel * n * esz);
-    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_x1 + b_mv, s);
+    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv, s);
     if (rc) return rc;
     uint8_t* base = static_cast<uint8_t*>(aux);
     uint16_t* orig = reinterpret_cast<uint16_t*>(base);
@@ -447,8 +447,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     int* perm = reinterpret_cast<int*>(base + b_orig + 2 * b_cand + b_state);
     uint8_t* W = base + b_orig + 2 * b_cand + b_state + b_perm;
     uint8_t* G = W + b_w;
-    uint8_t* x1 = G + b_g;
-    uint8_t* mvbuf = x1 + b_x1;
+    uint8_t* mvbuf = G + b_g;
 
     PanelState* hsp = static_cast<PanelState*>(ensure_pinned(sizeof(PanelState)));
     if (!hsp) return GF2E_ENOMEM;
@@ -559,22 +558,19 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         }
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
 
-        // X1 = W * (pivot rows); every other row (from r on, or all rows for
-        // the reduced form) += G * X1, where G is zero on the pivot rows;
-        // then X1 replaces the pivot rows.
+        // X1 = W * (pivot rows), in place over the pivot rows; then every
+        // other row (from r on, or all rows for the reduced form) += G * X1,
+        // where G is zero on the pivot rows, so that they keep X1.  Both
+        // products read their B operand into planes before writing C.
         const gf2e_mat Wm{W, rp, rp, rp};
-        const gf2e_mat P1{Ad + (r * lda + c0) * esz, rp, nc, lda};
-        gf2e_mat X1{x1, rp, nc, nc};
-        if ((rc = mul(e, f, &Wm, &P1, &X1, s))) return rc;
+        gf2e_mat X1{Ad + (r * lda + c0) * esz, rp, nc, lda};
+        if ((rc = mul(e, f, &Wm, &X1, &X1, s))) return rc;
         const int64_t lo = full ? 0 : r;
         if (m - lo > rp) {
             const gf2e_mat Gm{G + lo * rp * esz, m - lo, rp, rp};
             gf2e_mat Cm{Ad + (lo * lda + c0) * esz, m - lo, nc, lda};
             if ((rc = mul(e, f, &Gm, &X1, &Cm, s, true))) return rc;
         }
-        if (hipMemcpy2DAsync(Ad + (r * lda + c0) * esz, size_t(lda * esz), x1, size_t(nc * esz), size_t(nc * esz),
-                             size_t(rp), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return GF2E_EDEVICE;
         r += rp;
     }
     *rank = r;

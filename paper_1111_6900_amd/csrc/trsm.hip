@@ -193,11 +193,9 @@ int Ctx::trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32
     const int esz = elem_bytes(e);
     const int64_t nb = ceil_div(m, kTrsmBlock);
     const int64_t inv_bytes = round_up(nb * kTrsmBlock * kTrsmBlock * esz, 256);
-    const int64_t tmp_bytes = round_up(int64_t(kTrsmBlock) * n * esz, 256);
-    int rc = ensure_aux(inv_bytes + tmp_bytes, s);
+    int rc = ensure_aux(inv_bytes, s);
     if (rc) return rc;
     uint8_t* Tinv = static_cast<uint8_t*>(aux);
-    uint8_t* tmp = Tinv + inv_bytes;
     const DevTables tabs = field_tables(e, f);
     if (!tabs.exp) return GF2E_ENOMEM;
     if (launch_trsm_invert(e, tabs, lower, unit, T->data, T->ld, m, Tinv, d_err, s) != hipSuccess) return GF2E_EDEVICE;
@@ -207,16 +205,13 @@ int Ctx::trsm(int lower, int unit, const gf2e_mat* T, gf2e_mat* B, int e, uint32
     auto solve = [&](auto&& self, int64_t q0, int64_t q1) -> int {
         const int64_t R0 = q0 * kTrsmBlock, R1 = std::min(m, q1 * kTrsmBlock);
         if (q1 - q0 == 1) {
+            // X_q = inv(T_qq) * B_q in place: the product slices B_q into its
+            // planes before its last kernel writes C, all in stream order.
             const int64_t bs = R1 - R0;
             const gf2e_mat Ti = sub(&inv_all, esz, R0, 0, bs, bs);
             const gf2e_mat Bq = sub(B, esz, R0, 0, bs, n);
-            gf2e_mat Xq{tmp, bs, n, n};
-            int r = mul(e, f, &Ti, &Bq, &Xq, s);
-            if (r) return r;
-            if (hipMemcpy2DAsync(Bq.data, size_t(B->ld * esz), tmp, size_t(n * esz), size_t(n * esz), size_t(bs),
-                                 hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return GF2E_EDEVICE;
-            return GF2E_OK;
+            gf2e_mat Xq = Bq;
+            return mul(e, f, &Ti, &Bq, &Xq, s);
         }
         const int64_t mid = (q0 + q1) / 2, Rm = mid * kTrsmBlock;
         int r;
