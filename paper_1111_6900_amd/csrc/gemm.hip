@@ -438,14 +438,35 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
     fp4_store_parity<BM, BN, WM, WN>(acc, Ps, Np, tile_m, tile_n, wr, wc, lane);
 }
 
+// Tile of a workgroup, XCD-aware.  Workgroups are dispatched to the 8 XCDs
+// in turn (linear id modulo 8), and each XCD has its own L2.  When the
+// tile counts allow it, the tiles of a plane are cut into a 2 x 4 grid of
+// regions and XCD x takes region x, in row-major order inside it: an XCD
+// then reads half of A's row tiles and a quarter of B's column tiles instead
+// of all of A.  Otherwise the launch grid maps to tiles directly.
+__device__ __attribute__((always_inline)) inline void xcd_tile(int tiles_m, int tiles_n, int& tm, int& tn)
+{
+    constexpr int kXcds = 8, kRegM = 2, kRegN = 4;
+    tm = blockIdx.y;
+    tn = blockIdx.x;
+    if (tiles_m % kRegM || tiles_n % kRegN) return;
+    const int lin = int(blockIdx.y) * tiles_n + int(blockIdx.x);
+    const int xcd = lin % kXcds, local = lin / kXcds;
+    const int rm = tiles_m / kRegM, rn = tiles_n / kRegN;
+    tm = (xcd / kRegN) * rm + local / rn;
+    tn = (xcd % kRegN) * rn + local % rn;
+}
+
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
 __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_kernel(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
     int64_t Mp, int64_t Np, int64_t K64p, int tiles_m, int tiles_n)
 {
     const int64_t s = blockIdx.z;
+    int tm, tn;
+    xcd_tile(tiles_m, tiles_n, tm, tn);
     fp4_tile<BM, BN, WM, WN, KB, FA, FB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
-                                 Np, K64p, blockIdx.y, blockIdx.x);
+                                 Np, K64p, tm, tn);
 }
 
 // Products with little k: stages of one 128-bit k-block (K64p a multiple of
