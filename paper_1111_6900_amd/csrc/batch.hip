@@ -4,8 +4,8 @@
 //
 // After slicing, a product over any F_{2^e} is t(e) GF(2) plane products of
 // the same (m, n, k) (Section 5), so one persistent grouped kernel serves
-// every field: its work list holds (product, plane, tile) items, sorted by
-// decreasing k so the longest tiles start first, and workgroups take items
+// every field: its work list holds (product, planes, tile) items, sorted by
+// decreasing work so the longest start first, and workgroups take items
 // from a global counter until the list is exhausted.  Slicing and combining
 // run as one grouped launch each, dispatching on e per product.
 #include <hip/hip_runtime.h>
@@ -58,6 +58,7 @@ struct BatchGraph {
 namespace {
 
 constexpr int kMaxCachedBatches = 8;
+
 
 template <class T>
 void put(std::vector<uint8_t>& key, const T& v)
@@ -133,9 +134,13 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
                         (d.K64p * 64 <= (int64_t(1) << 24) ? 0 : 2);
         const GemmShape sh = gemm_shape(kClassKinds[cls]);
         const int tm = int(ceil_div(d.m, sh.bm)), tn = int(ceil_div(d.n, sh.bn));
-        for (int s = 0; s < d.T; ++s)
+        // Planes of one tile per item: as many as keep an item below
+        // kItemKWords k-words in all, so that items stay comparable.
+        const int group = int(std::clamp<int64_t>(kItemKWords / d.K64p, 1, d.T));
+        for (int s = 0; s < d.T; s += group)
             for (int a = 0; a < tm; ++a)
-                for (int b = 0; b < tn; ++b) items[cls].push_back({int32_t(i), s, a, b});
+                for (int b = 0; b < tn; ++b)
+                    items[cls].push_back({int32_t(i), s, a, b, std::min(group, d.T - s)});
     }
     const char* shuffle = std::getenv("GF2E_BATCH_SHUFFLE");
     for (int cls = 0; cls < kNumClasses; ++cls) {
@@ -145,7 +150,7 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
             std::shuffle(v.begin(), v.end(), rng);
         } else {
             std::stable_sort(v.begin(), v.end(), [&](const WorkItem& x, const WorkItem& y) {
-                return prods[x.prod].K64p > prods[y.prod].K64p;
+                return prods[x.prod].K64p * x.nplanes > prods[y.prod].K64p * y.nplanes;
             });
         }
         bg->n_items[cls] = int(v.size());

@@ -177,10 +177,10 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) void gemm_mfm
         if (it >= nitems) break;
         const WorkItem w = items[it];
         const BatchProduct& P = prods[w.prod];
-        const int64_t s = w.plane;
-        mfma_tile<BM, BN, WM, WN>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
-                                  P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
-                                  w.tile_n);
+        for (int64_t s = w.plane; s < w.plane + w.nplanes; ++s)
+            mfma_tile<BM, BN, WM, WN>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
+                                      P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
+                                      w.tile_n);
     }
 }
 
@@ -469,26 +469,27 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
                                  Np, K64p, tm, tn);
 }
 
-// Products with little k: stages of one 128-bit k-block (K64p a multiple of
-// 2), and each workgroup runs planes s0..s1-1 of its tile as one pipeline of
-// stages, so that the operands of the next plane load while the current one
-// computes and writes its words.  A launch of many planes over a short k is
-// then not bound by one load latency per plane.
-template <int BM, int BN, int WM, int WN, int FA, int FB>
+// Planes s0..s1-1 of one tile as one pipeline of stages (KB 128-bit
+// k-blocks each, K64p a multiple of 2 KB), so that the operands of the next
+// plane load while the current one computes and writes its words.  Products
+// with little k (KB = 1) and the persistent work items (several planes of a
+// tile) are then not bound by one load latency per plane.
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
 __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P, int s0, int s1,
     int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
 {
     using TL = MfmaTile<BM, BN, WM, WN>;
     constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
-    constexpr int CH = 4;  // 32-bit chunks per row per 128-bit stage
+    constexpr int CH = 4 * KB;  // 32-bit chunks per row per stage of KB 128-bit k-blocks
     __shared__ Fp4Side<BM, CH, FA, false> sa;
     __shared__ Fp4Side<BN, CH, FB, true> sb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
-    const int nst = int(K64p / 2);     // stages per plane
+    const int nst = int(K64p / (2 * KB));  // stages per plane
     const int G = (s1 - s0) * nst;     // stages of all planes
     static_assert(BM % 64 == 0 && NT % 64 == 0, "a wave stages rows of one side only");
+    static_assert(KB == 1 || KB == 2, "stages of one or two 128-bit k-blocks");
 
     v4f acc[FM][FN];
 #pragma unroll
@@ -496,7 +497,7 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    using Stage = uint64_t[RPT][2];
+    using Stage = uint64_t[RPT][2 * KB];
     auto gload = [&](int g, Stage& dst) {
         const int64_t s = s0 + g / nst, st = g % nst;
         const uint64_t* Ap = Apl + s * K64p * Mp + int64_t(tile_m) * BM;
@@ -509,7 +510,7 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
                 const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
                 const int64_t ld = isA ? Mp : Np;
 #pragma unroll
-                for (int w = 0; w < 2; ++w) dst[q][w] = src[(st * 2 + w) * ld];
+                for (int w = 0; w < 2 * KB; ++w) dst[q][w] = src[(st * 2 * KB + w) * ld];
             }
         }
     };
@@ -531,16 +532,20 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
     };
     const int g4 = lane >> 4, l16 = lane & 15;
     auto compute = [&](int buf) {
-        v8i a[FM], b[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) a[i] = sa.get(buf, g4, wr * WM + 16 * i + l16);
+        for (int kb = 0; kb < KB; ++kb) {
+            v8i a[FM], b[FN];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) b[j] = sb.get(buf, g4, wc * WN + 16 * j + l16);
+            for (int i = 0; i < FM; ++i) a[i] = sa.get(buf, 4 * kb + g4, wr * WM + 16 * i + l16);
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < FN; ++j) b[j] = sb.get(buf, 4 * kb + g4, wc * WN + 16 * j + l16);
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0, 0, 0, 0);
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0, 0, 0, 0);
+        }
     };
 
     Stage sr;
@@ -571,10 +576,12 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
     int64_t Mp, int64_t Np, int64_t K64p)
 {
     const int s0 = int(blockIdx.z) * ppw, s1 = min(T, s0 + ppw);
-    fp4_planes_tile<BM, BN, WM, WN, FA, FB>(Apl, Bpl, P, s0, s1, Mp, Np, K64p, blockIdx.y, blockIdx.x);
+    fp4_planes_tile<BM, BN, WM, WN, 1, FA, FB>(Apl, Bpl, P, s0, s1, Mp, Np, K64p, blockIdx.y, blockIdx.x);
 }
 
-template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
+// Persistent form: workgroups take (product, planes, tile) items in order
+// from *counter; the planes of an item run as one pipeline.
+template <int BM, int BN, int WM, int WN, int FA, int FB>
 __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_persistent(
     const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
     int* __restrict__ counter)
@@ -588,10 +595,9 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
         if (it >= nitems) break;
         const WorkItem w = items[it];
         const BatchProduct& P = prods[w.prod];
-        const int64_t s = w.plane;
-        fp4_tile<BM, BN, WM, WN, KB, FA, FB>(P.Apl + s * P.K64p * P.Mp, P.Bpl + s * P.K64p * P.Np,
-                                     P.P + s * P.Mp * (P.Np / 64), P.Mp, P.Np, P.K64p, w.tile_m,
-                                     w.tile_n);
+        // K64p is a multiple of 4 here: stages of two 128-bit k-blocks
+        fp4_planes_tile<BM, BN, WM, WN, 2, FA, FB>(P.Apl, P.Bpl, P.P, w.plane, w.plane + w.nplanes, P.Mp, P.Np,
+                                                   P.K64p, w.tile_m, w.tile_n);
     }
 }
 
@@ -761,10 +767,10 @@ int persistent_grid(int kind)
         case GEMM_MFMA_256x256_W8: return persistent_blocks<256, 256, 128, 64>();
         case GEMM_MFMA_128x128: return persistent_blocks<128, 128, 64, 64>();
         case GEMM_FP4_256x256_W8:
-            return blocks_filling_device(gemm_fp4_persistent<256, 256, 128, 64, 2, kSplit, kPacked>,
+            return blocks_filling_device(gemm_fp4_persistent<256, 256, 128, 64, kSplit, kPacked>,
                                          MfmaTile<256, 256, 128, 64>::kThreads);
         case GEMM_FP4_128x128:
-            return blocks_filling_device(gemm_fp4_persistent<128, 128, 64, 64, 2, kPacked, kPacked>,
+            return blocks_filling_device(gemm_fp4_persistent<128, 128, 64, 64, kPacked, kPacked>,
                                          MfmaTile<128, 128, 64, 64>::kThreads);
         default: return 0;
     }
@@ -787,12 +793,12 @@ hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const Wor
                                counter);
             break;
         case GEMM_FP4_256x256_W8:
-            hipLaunchKernelGGL((gemm_fp4_persistent<256, 256, 128, 64, 2, kSplit, kPacked>), dim3(grid),
+            hipLaunchKernelGGL((gemm_fp4_persistent<256, 256, 128, 64, kSplit, kPacked>), dim3(grid),
                                dim3(MfmaTile<256, 256, 128, 64>::kThreads), 0, s, prods, items, nitems,
                                counter);
             break;
         case GEMM_FP4_128x128:
-            hipLaunchKernelGGL((gemm_fp4_persistent<128, 128, 64, 64, 2, kPacked, kPacked>), dim3(grid),
+            hipLaunchKernelGGL((gemm_fp4_persistent<128, 128, 64, 64, kPacked, kPacked>), dim3(grid),
                                dim3(MfmaTile<128, 128, 64, 64>::kThreads), 0, s, prods, items, nitems,
                                counter);
             break;

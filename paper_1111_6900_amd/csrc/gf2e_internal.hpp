@@ -94,10 +94,14 @@ struct BatchProduct {
     int32_t combine_blocks;
 };
 
-// One tile of one plane product in a persistent launch.
+// One tile of planes plane..plane+nplanes-1 of a product in a persistent
+// launch (the fp4 kernels run those planes as one pipeline).
 struct WorkItem {
-    int32_t prod, plane, tile_m, tile_n;
+    int32_t prod, plane, tile_m, tile_n, nplanes;
 };
+// Planes per work item in the batched and served forms: as many as keep an
+// item within this many k-words in all (at least one plane).
+constexpr int64_t kItemKWords = 256;
 
 hipError_t launch_batched_slice(const BatchProduct* prods, int count, int max_blocks, int* err,
                                 hipStream_t s);

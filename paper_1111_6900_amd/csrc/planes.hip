@@ -63,6 +63,27 @@ __device__ inline void store_operands(const uint64_t (&planes)[E], uint64_t* dst
     }
 }
 
+// Loads nbytes (at most 16) bytes at p, zero beyond, with the aligned
+// dwords that hold them: p need not be aligned, and no dword is read that
+// holds none of the bytes (so nothing outside the buffer's aligned words).
+__device__ __attribute__((always_inline)) inline uint4 load16_any(const uint8_t* p, int nbytes)
+{
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(p);
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(pa & ~uintptr_t(3));
+    const int off = int(pa & 3);
+    uint32_t d[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) d[i] = 4 * i < off + nbytes ? w[i] : 0u;
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t x = __builtin_amdgcn_alignbyte(d[j + 1], d[j], uint32_t(off));
+        const int b = nbytes - 4 * j;
+        o[j] = b >= 4 ? x : b <= 0 ? 0u : x & ((1u << (8 * b)) - 1u);
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 // Row slicing of one plane word: row r of A, k-bits [64kw, 64kw+64).
 template <int E, int SID>
 __device__ __attribute__((always_inline)) inline void slice_row_word(const void* __restrict__ A, int64_t lda, int64_t m, int64_t k,
@@ -75,31 +96,34 @@ __device__ __attribute__((always_inline)) inline void slice_row_word(const void*
     const int64_t c0 = kw * 64;
     if (r < m && c0 < k) {
         const elem_t* row = reinterpret_cast<const elem_t*>(A) + r * lda + c0;
-        const int64_t valid = (k - c0) < 64 ? (k - c0) : 64;
+        const int valid = int((k - c0) < 64 ? (k - c0) : 64);
+        // 16-byte pieces of the row: vector loads when aligned and whole,
+        // else the aligned dwords that hold the piece's valid bytes
+        constexpr int EB = int(sizeof(elem_t)), NQ = 4 * EB;
+        const uint8_t* rb = reinterpret_cast<const uint8_t*>(row);
+        const bool fast = valid == 64 && (reinterpret_cast<uintptr_t>(rb) & 15) == 0;
+        uint4 q[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            q[i] = fast ? reinterpret_cast<const uint4*>(rb)[i] : load16_any(rb + 16 * i, valid * EB - 16 * i);
         if constexpr (E <= 8) {
-            if (valid == 64 && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
-                const uint4* v = reinterpret_cast<const uint4*>(row);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint4 x = v[q];
-                    lo[2 * q] = uint64_t(x.x) | (uint64_t(x.y) << 32);
-                    lo[2 * q + 1] = uint64_t(x.z) | (uint64_t(x.w) << 32);
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 64; ++c)
-                    if (c < valid) lo[c >> 3] |= uint64_t(row[c]) << (8 * (c & 7));
+            for (int i = 0; i < 4; ++i) {
+                lo[2 * i] = uint64_t(q[i].x) | (uint64_t(q[i].y) << 32);
+                lo[2 * i + 1] = uint64_t(q[i].z) | (uint64_t(q[i].w) << 32);
             }
 #pragma unroll
             for (int g = 0; g < 8; ++g) bad |= bytes_out_of_field(lo[g], E);
         } else {
+            // piece i holds elements 8i..8i+7 as uint16: split low and high bytes
 #pragma unroll
-            for (int c = 0; c < 64; ++c) {
-                if (c < valid) {
-                    const uint32_t x = row[c];
-                    bad |= (x >> E) != 0;
-                    lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
-                    hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t w4[4] = {q[i].x, q[i].y, q[i].z, q[i].w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    bad |= ((w4[h] & 0xFFFFu) >> E) != 0 || ((w4[h] >> 16) >> E) != 0;
+                    lo[i] |= uint64_t((w4[h] & 0xFFu) | ((w4[h] >> 8) & 0xFF00u)) << (16 * h);
+                    hi[i] |= uint64_t(((w4[h] >> 8) & 0xFFu) | ((w4[h] >> 16) & 0xFF00u)) << (16 * h);
                 }
             }
         }
@@ -110,48 +134,25 @@ __device__ __attribute__((always_inline)) inline void slice_row_word(const void*
     store_operands<E, SID, false>(pl, planes + kw * Mp + r, K64p * Mp);
 }
 
-// Bit-planes of one column word: column j of B, k-bits [64kw, 64kw+64).
-// Consecutive threads take consecutive columns, so every load is coalesced.
-template <int E>
-__device__ __attribute__((always_inline)) inline void load_col_planes(const void* __restrict__ B, int64_t ldb,
-                                                                       int64_t k, int64_t n, int* __restrict__ err,
-                                                                       int64_t j, int64_t kw, uint64_t (&pl)[E])
-{
-    using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
-    uint64_t lo[8] = {}, hi[8] = {};
-    bool bad = false;
-    const int64_t r0 = kw * 64;
-    if (j < n && r0 < k) {
-        const elem_t* col = reinterpret_cast<const elem_t*>(B) + r0 * ldb + j;
-        const int64_t valid = (k - r0) < 64 ? (k - r0) : 64;
-#pragma unroll
-        for (int c = 0; c < 64; ++c) {
-            if (c < valid) {
-                const uint32_t x = col[c * ldb];
-                bad |= (x >> E) != 0;
-                lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
-                if constexpr (E > 8) hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));
-            }
-        }
-    }
-    if (bad) atomicOr(err, 1);
-    bytes_to_planes<E>(lo, hi, pl);
-}
-
 // Bit-planes of one column word for a block of 64 columns (one wave per
 // block): the 64 x 64 tile of B (k-bits [64kw, 64kw+64), columns
 // j0..j0+63) is read with 16-byte row pieces where they are aligned, staged
-// in LDS row-major, and each lane then reads its own column from LDS.  That
-// replaces 64 narrow global loads per lane by a few wide ones.
+// in LDS row-major (tile_mem: col_tile_bytes of LDS for this wave), and each
+// lane then reads its own column from LDS.  That replaces 64 narrow global
+// loads per lane by a few wide ones.  Every thread of the block calls it.
+// LDS bytes of one wave's tile for elements of EB bytes (rows padded by 16).
+constexpr int col_tile_bytes(int EB) { return 64 * (64 * EB + 16); }
+
 template <int E>
 __device__ __attribute__((always_inline)) inline void load_col_planes_tile(const void* __restrict__ B, int64_t ldb,
                                                                             int64_t k, int64_t n,
                                                                             int* __restrict__ err, int64_t j0,
-                                                                            int64_t kw, int lane, uint64_t (&pl)[E])
+                                                                            int64_t kw, int lane, uint8_t* tile_mem,
+                                                                            uint64_t (&pl)[E])
 {
     using elem_t = typename std::conditional<(E > 8), uint16_t, uint8_t>::type;
     constexpr int EB = int(sizeof(elem_t)), RB = 64 * EB, CH = RB / 16, PE = 16 / EB;
-    __shared__ __align__(16) uint8_t tile[64][RB + 16];
+    auto tile = reinterpret_cast<uint8_t(*)[RB + 16]>(tile_mem);  // this wave's 64 rows
     const elem_t* base = static_cast<const elem_t*>(B);
     const int64_t r0 = kw * 64;
 #pragma unroll
@@ -161,15 +162,10 @@ __device__ __attribute__((always_inline)) inline void load_col_planes_tile(const
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (gr < k && gc < n) {
             const elem_t* src = base + gr * ldb + gc;
-            if (gc + PE <= n && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            if (gc + PE <= n && (reinterpret_cast<uintptr_t>(src) & 15) == 0)
                 v = *reinterpret_cast<const uint4*>(src);
-            } else {
-                uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-                for (int e = 0; e < PE; ++e)
-                    if (gc + e < n) w[e * EB / 4] |= uint32_t(src[e]) << (8 * ((e * EB) % 4));
-                v = make_uint4(w[0], w[1], w[2], w[3]);
-            }
+            else
+                v = load16_any(reinterpret_cast<const uint8_t*>(src), int(n - gc < PE ? n - gc : PE) * EB);
         }
         *reinterpret_cast<uint4*>(&tile[row][pc * 16]) = v;
     }
@@ -185,17 +181,6 @@ __device__ __attribute__((always_inline)) inline void load_col_planes_tile(const
     }
     if (bad) atomicOr(err, 1);
     bytes_to_planes<E>(lo, hi, pl);
-}
-
-// Column slicing of one plane word into the schedule's B-side operands.
-template <int E, int SID>
-__device__ __attribute__((always_inline)) inline void slice_col_word(const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n,
-                                      uint64_t* __restrict__ planes, int64_t Np, int64_t K64p,
-                                      int* __restrict__ err, int64_t j, int64_t kw)
-{
-    uint64_t pl[E];
-    load_col_planes<E>(B, ldb, k, n, err, j, kw, pl);
-    store_operands<E, SID, true>(pl, planes + kw * Np + j, K64p * Np);
 }
 
 // Alpha-power slicing of one column word (alpha = x, the class of x in
@@ -339,9 +324,10 @@ __global__ __launch_bounds__(kColBlock) void slice_cols_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
+    __shared__ __align__(16) uint8_t tile[col_tile_bytes(E > 8 ? 2 : 1)];
     const int64_t j0 = int64_t(blockIdx.x) * kColBlock, kw = blockIdx.y;
     uint64_t pl[E];
-    load_col_planes_tile<E>(B, ldb, k, n, err, j0, kw, threadIdx.x, pl);
+    load_col_planes_tile<E>(B, ldb, k, n, err, j0, kw, threadIdx.x, tile, pl);
     store_operands<E, SID, true>(pl, planes + kw * Np + j0 + threadIdx.x, K64p * Np);
 }
 
@@ -350,9 +336,10 @@ __global__ __launch_bounds__(kColBlock) void slice_cols_alpha_kernel(
     const void* __restrict__ B, int64_t ldb, int64_t k, int64_t n, uint32_t f, uint64_t* __restrict__ planes,
     int64_t Np, int64_t K64p, int* __restrict__ err)
 {
+    __shared__ __align__(16) uint8_t tile[col_tile_bytes(E > 8 ? 2 : 1)];
     const int64_t j0 = int64_t(blockIdx.x) * kColBlock, kw = blockIdx.y;
     uint64_t cur[E];
-    load_col_planes_tile<E>(B, ldb, k, n, err, j0, kw, threadIdx.x, cur);
+    load_col_planes_tile<E>(B, ldb, k, n, err, j0, kw, threadIdx.x, tile, cur);
     store_alpha_blocks<E>(cur, f, planes, Np, K64p, j0 + threadIdx.x, kw);
 }
 
@@ -451,10 +438,16 @@ __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProd
     }
     job -= P.slice_a_blocks;
     if (job < P.slice_b_blocks) {
+        // 256 consecutive columns of one k-word; each wave slices 64 of them
+        // through its own LDS tile (the branch is uniform in the block)
+        __shared__ __align__(16) uint8_t tiles[kThreads / 64][col_tile_bytes(EMAX > 8 ? 2 : 1)];
         const int64_t cb_count = P.Np / kThreads;
-        const int64_t j = (job % cb_count) * kThreads + threadIdx.x, kw = job / cb_count;
+        const int wave = int(threadIdx.x) / 64, lane = int(threadIdx.x) % 64;
+        const int64_t j0 = (job % cb_count) * kThreads + 64 * wave, kw = job / cb_count;
         with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
-            slice_col_word<E, SID>(P.B, P.ldb, P.k, P.n, P.Bpl, P.Np, P.K64p, err, j, kw);
+            uint64_t pl[E];
+            load_col_planes_tile<E>(P.B, P.ldb, P.k, P.n, err, j0, kw, lane, tiles[wave], pl);
+            store_operands<E, SID, true>(pl, P.Bpl + kw * P.Np + j0 + lane, P.K64p * P.Np);
         });
     }
 }

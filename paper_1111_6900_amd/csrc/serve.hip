@@ -93,6 +93,7 @@ struct Request {
     Plan plan{};
     int64_t footprint = 0, arena_off = -1;
     int slot = -1, cls = 0, tm = 0, tn = 0;
+    int group = 1;  // planes per work item
     int64_t total_items = 0, next_item = 0;
     std::atomic<int> state{PENDING};
     int status = GF2E_OK;
@@ -233,13 +234,14 @@ bool Server::issue_iteration()
     for (Request* r : admitted) {
         if (budget <= 0 || room <= 0) break;
         const GemmShape sh = gemm_shape(kClassKinds[r->cls]);
-        const int64_t item_macs = int64_t(sh.bm) * sh.bn * r->d.K64p * 64;
+        const int64_t plane_macs = int64_t(sh.bm) * sh.bn * r->d.K64p * 64;
         while (r->next_item < r->total_items && budget > 0 && room > 0) {
             const int64_t it = r->next_item++;
-            const int64_t per_plane = int64_t(r->tm) * r->tn;
-            const int s = int(it / per_plane), rem = int(it % per_plane);
-            cls_items[r->cls].push_back({int32_t(r->slot), s, rem / r->tn, rem % r->tn});
-            budget -= item_macs;
+            const int64_t per_group = int64_t(r->tm) * r->tn;
+            const int s = int(it / per_group) * r->group, rem = int(it % per_group);
+            const int np = std::min(r->group, r->d.T - s);
+            cls_items[r->cls].push_back({int32_t(r->slot), s, rem / r->tn, rem % r->tn, np});
+            budget -= plane_macs * np;
             room -= 1;
         }
         if (r->next_item == r->total_items) finishing.push_back(r);
@@ -411,7 +413,10 @@ int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B
     const GemmShape sh = gemm_shape(kClassKinds[r->cls]);
     r->tm = int(ceil_div(std::max<int64_t>(m, 1), sh.bm));
     r->tn = int(ceil_div(std::max<int64_t>(n, 1), sh.bn));
-    r->total_items = (m > 0 && n > 0 && k > 0) ? int64_t(r->plan.T) * r->tm * r->tn : 0;
+    // One plane per item: an iteration's quantum then splits into many items,
+    // which keeps the device full and the latency of small requests low.
+    r->group = 1;
+    r->total_items = (m > 0 && n > 0 && k > 0) ? ceil_div(r->plan.T, r->group) * r->tm * r->tn : 0;
     {
         DeviceGuard guard(s->ctx->device);
         if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) return GF2E_EDEVICE;
