@@ -236,6 +236,20 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+class PreparedBatch:
+    """A batch whose descriptors are marshalled once (see Context.prepare_batched).
+    It keeps its tensors alive; launch() enqueues the batch on a stream."""
+
+    def __init__(self, ctx, As, Bs, outs, args):
+        self.ctx, self.As, self.Bs, self.outs, self._args = ctx, list(As), list(Bs), list(outs), args
+
+    def launch(self, stream=None):
+        n, MA, MB, MC, E, F = self._args
+        _check(lib().gf2e_mul_batched(self.ctx.handle, n, MA, MB, MC, E, F, _stream_handle(stream)),
+               "gf2e_mul_batched")
+        return self.outs
+
+
 class Context:
     """Owns a gf2e context (workspace, tuning cache) on one device."""
 
@@ -346,6 +360,14 @@ class Context:
         _check(lib().gf2e_mul_batched(self.handle, n, MA, MB, MC, E, F, _stream_handle(stream)),
                "gf2e_mul_batched")
         return outs
+
+    def prepare_batched(self, As, Bs, es, fs, outs=None) -> "PreparedBatch":
+        """The marshalled arguments of one batch, to launch it again and again
+        (the library replays its cached graph for the same descriptors)."""
+        if outs is None:
+            outs = [torch.empty((a.size(0), b.size(1)), dtype=a.dtype, device=a.device)
+                    for a, b in zip(As, Bs)]
+        return PreparedBatch(self, As, Bs, outs, self._batch_args(As, Bs, outs, es, fs))
 
     def mul_batched(self, As, Bs, es, fs, outs=None, stream=None):
         outs = self.mul_batched_async(As, Bs, es, fs, outs=outs, stream=stream)

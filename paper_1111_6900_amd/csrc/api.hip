@@ -29,7 +29,17 @@ DeviceGuard::~DeviceGuard()
 
 int elem_bytes(int e) { return e <= 8 ? 1 : 2; }
 
-bool field_ok(int e, uint32_t f) { return e >= 2 && e <= kMaxE && is_irreducible(e, f); }
+bool field_ok(int e, uint32_t f)
+{
+    if (e < 2 || e > kMaxE) return false;
+    // The last irreducible f seen per degree (per thread): batches repeat a
+    // few fields many times.
+    thread_local uint32_t known[kMaxE + 1] = {};
+    if (known[e] == f) return true;
+    if (!is_irreducible(e, f)) return false;
+    known[e] = f;
+    return true;
+}
 
 int check_mat(const gf2e_mat* M)
 {

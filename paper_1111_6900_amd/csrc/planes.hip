@@ -301,9 +301,41 @@ __device__ __attribute__((always_inline)) inline void combine_word(const uint64_
             return;
         }
     }
+    // Unaligned or partial run: the dwords inside it are written whole, the
+    // bytes of the partial dwords at its ends one by one (the neighbouring
+    // runs own the other bytes of those dwords).
+    constexpr int EB = int(sizeof(elem_t)), NW = 16 * EB;
+    uint32_t o[NW];
 #pragma unroll
-    for (int b = 0; b < 64; ++b)
-        if (b < valid) dst[b] = acc ? elem_t(dst[b] ^ out[b]) : out[b];
+    for (int j = 0; j < NW; ++j) {
+        if constexpr (EB == 1)
+            o[j] = uint32_t(out[4 * j]) | (uint32_t(out[4 * j + 1]) << 8) | (uint32_t(out[4 * j + 2]) << 16) |
+                   (uint32_t(out[4 * j + 3]) << 24);
+        else
+            o[j] = uint32_t(out[2 * j]) | (uint32_t(out[2 * j + 1]) << 16);
+    }
+    const int nbytes = int(valid) * EB;
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(dst);
+    const int off = int(pa & 3);
+    uint32_t* aw = reinterpret_cast<uint32_t*>(pa & ~uintptr_t(3));
+#pragma unroll
+    for (int t = 0; t <= NW; ++t) {
+        const int first = 4 * t - off;  // run offset of the dword's byte 0
+        if (first >= nbytes) break;
+        const uint32_t lo = t > 0 ? o[t - 1] : 0u, hi = t < NW ? o[t] : 0u;
+        const uint32_t v = off ? __builtin_amdgcn_alignbyte(hi, lo, uint32_t(4 - off)) : hi;
+        if (first >= 0 && first + 4 <= nbytes) {
+            aw[t] = acc ? aw[t] ^ v : v;
+        } else {
+            uint8_t* ab = reinterpret_cast<uint8_t*>(aw + t);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (first + b >= 0 && first + b < nbytes) {
+                    const uint8_t x = uint8_t(v >> (8 * b));
+                    ab[b] = acc ? uint8_t(ab[b] ^ x) : x;
+                }
+        }
+    }
 }
 
 template <int E, int SID>

@@ -136,3 +136,25 @@ def test_tune_batched_keeps_results(g):
     for p, ((e, f, m, k, n), (a, b)) in enumerate(zip(specs, mats)):
         assert (host(outs[p]) == oracle.matmul(a, b, e, f)).all(), p
     ctx.close()
+
+
+def test_prepared_batch_replays(g):
+    """A batch marshalled once replays the cached graph: its results equal the
+    oracle's after the inputs change between launches."""
+    specs = workload.batch_specs(48, lo=16, hi=300, tag=4)
+    mats, As, Bs, es, fs = make_batch(g, specs, tag=9)
+    ctx = g.Context(0)
+    prep = ctx.prepare_batched(As, Bs, es, fs)
+    gen = np.random.default_rng(91)
+    for rnd in range(3):
+        print(f"prepared batch launch {rnd}", flush=True)
+        outs = prep.launch()
+        ctx.sync()
+        for p, ((e, f, m, k, n), (a, b)) in enumerate(zip(specs, mats)):
+            assert (host(outs[p]) == oracle.matmul(a, b, e, f)).all(), (rnd, p)
+        for p in range(0, len(specs), 5):
+            new = workload.field_matrix(gen, *mats[p][1].shape, es[p])
+            Bs[p].copy_(to_dev(g, new, es[p]))
+            mats[p] = (mats[p][0], new)
+    assert ctx.batch_info()["graph_builds"] == 1
+    ctx.close()
