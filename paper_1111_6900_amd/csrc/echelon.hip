@@ -118,10 +118,10 @@ constexpr int kSelRows = 256;   // rows per workgroup of the tournament
 constexpr int kSelParts = 4;    // lanes per row
 constexpr int kProbeRows = 128; // rows of the probe (2 kPanel: full rank unless the rows are special)
 
-template <int ROWS, int PARTS, bool LDS_TABS>
+template <int ROWS, int PARTS, bool LDS_TABS, bool FINAL>
 __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16_t* orig, int64_t r, int bc,
-                                                                    const int* in, int64_t ncand, int* out, int final,
-                                                                    PanelState* st, DevField F)
+                                                                    const int* in, int64_t ncand, int* out,
+                                                                    PanelState* st, DevField F, int wide, void* W)
 {
     constexpr int NT = ROWS * PARTS, CPT = kPanel / PARTS;
     static_assert(kPanel % PARTS == 0 && 64 % PARTS == 0 && NT <= 1024, "rows lie within one wave");
@@ -129,6 +129,8 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
     __shared__ int pivs[kPanel];
     __shared__ int plog[kPanel];
+    __shared__ int alog[FINAL ? kPanel : 1];    // the pivot row's coefficients (logs)
+    __shared__ int colpiv[FINAL ? kPanel : 1];  // pivot index of each panel column, -1 if none
     __shared__ int lead;
     const int tid = threadIdx.x, rl = tid / PARTS, part = tid % PARTS, lane = tid & 63;
     const int q = int(F.q);
@@ -137,6 +139,9 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     uint32_t v[CPT];  // v[i]: column part + PARTS * i of this row
 #pragma unroll
     for (int i = 0; i < CPT; ++i) v[i] = row >= 0 ? orig[(r + row) * kPanel + part + PARTS * i] : 0u;
+    // a[i]: this row as a combination of the pivot rows found so far, indexed
+    // by their pivot columns (part + PARTS * i); the final level only
+    uint32_t a[FINAL ? CPT : 1] = {};
     // tables in LDS when they fit (e <= 10), else read from the device copy;
     // a compile-time choice, so that the lookups are LDS (or global) loads
     if constexpr (LDS_TABS) {
@@ -145,36 +150,50 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     }
     const uint16_t* ex = LDS_TABS ? sexp : F.exp;
     const uint32_t* lg = LDS_TABS ? slog : F.log;
-    if (tid < kPanel) pivs[tid] = INT_MAX;
+    if (tid < kPanel) {
+        pivs[tid] = INT_MAX;
+        if constexpr (FINAL) colpiv[tid] = -1;
+    }
     __syncthreads();
     bool used = row < 0;
     int npiv = 0;
+    int my_t = -1, my_lead = 0;  // a pivot row's index and log of 1 / its pivot
     // Offers this row as the pivot of column c (the first row with a nonzero
     // entry there wins); only the lane owning column c has a say.
-    auto offer = [&](int c, bool nonzero) {
+    auto offer = [&](int c, bool nonzero) __attribute__((always_inline)) {
         const uint64_t bal = __ballot(c < bc && !used && part == c % PARTS && nonzero);
         if (bal && lane == __ffsll(static_cast<long long>(bal)) - 1) atomicMin(&pivs[c], rl);
     };
     offer(0, v[0] != 0);
     // Step J eliminates column J; the steps are instantiated one by one, so
-    // that J is a constant in each.
-    auto step = [&]<int J>() {
+    // that J is a constant in each.  The final level eliminates column J
+    // from every other row, pivot rows included (Gauss-Jordan), and carries
+    // the combinations along, so that each pivot row ends as its row of
+    // K^{-1} times its pivot.
+    auto step = [&]<int J>() __attribute__((always_inline)) {  // inlined, so v and a stay in registers
         if (J >= bc) return;  // uniform
-        __syncthreads();      // pivs[J] is final; plog and lead of step J - 1 are no longer read
+        __syncthreads();      // pivs[J] is final; plog, alog and lead of step J - 1 are no longer read
         const int p = pivs[J];
         if (p == INT_MAX) {  // no pivot in column J: offer column J + 1 as it is
             if constexpr (J + 1 < kPanel) offer(J + 1, v[(J + 1) / PARTS] != 0);
             return;
         }
+        if constexpr (FINAL)  // the pivot row's own coefficient
+            a[J / PARTS] = rl == p && part == J % PARTS ? 1u : a[J / PARTS];
         if (rl == p) {  // the pivot row publishes the logarithms of its entries (2q for zeros)
 #pragma unroll
-            for (int i = 0; i < CPT; ++i) plog[part + PARTS * i] = int(lg[v[i]]);
+            for (int i = 0; i < CPT; ++i) {
+                plog[part + PARTS * i] = int(lg[v[i]]);
+                if constexpr (FINAL) alog[part + PARTS * i] = int(lg[a[i]]);
+            }
             if (part == J % PARTS) lead = q - int(lg[v[J / PARTS]]);
         }
+        if constexpr (FINAL)
+            if (tid == 0) colpiv[J] = npiv;
         __syncthreads();
         if (rl == p) {
             if (part == 0) {
-                if (final) {
+                if constexpr (FINAL) {
                     st->rows[npiv] = row;
                     st->cols[npiv] = J;
                 } else {
@@ -182,126 +201,44 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
                 }
             }
             used = true;
+            my_t = npiv;
+            my_lead = lead;
         }
         ++npiv;  // uniform across the workgroup
         // x: this row's entry in column J, held by the lane owning column J
         const uint32_t x = __shfl(v[J / PARTS], (lane & ~(PARTS - 1)) | (J % PARTS));
         // lf: log of the multiplier x / pivot, or 2q (a zero product) for
-        // rows that are used or have nothing to eliminate; no branch per row
+        // rows with nothing to eliminate; no branch per row
         int lf = int(lg[x]) + lead;
         lf -= lf >= q ? q : 0;
-        lf = used || x == 0 ? 2 * q : lf;
+        const bool skip = FINAL ? (rl == p || x == 0) : (used || x == 0);
+        lf = skip ? 2 * q : lf;
 #pragma unroll
-        for (int i = 0; i < CPT; ++i)
+        for (int i = 0; i < CPT; ++i) {
             if (part + PARTS * i > J) v[i] ^= ex[lf + plog[part + PARTS * i]];
+            if constexpr (FINAL) {
+                const uint32_t d = ex[lf + alog[part + PARTS * i]];
+                a[i] = part + PARTS * i <= J ? a[i] ^ d : a[i];
+            }
+        }
         if constexpr (J + 1 < kPanel) offer(J + 1, v[(J + 1) / PARTS] != 0);
     };
-    [&]<int... J>(std::integer_sequence<int, J...>) {
+    [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
         (step.template operator()<J>(), ...);
     }(std::make_integer_sequence<int, kPanel>{});
-    if (tid == 0) {
-        if (final) st->rp = npiv;
-        else
+    if constexpr (FINAL) {
+        if (tid == 0) st->rp = npiv;
+        // W[t][s] = coefficient of pivot row s in pivot row t, over its pivot
+        if (my_t >= 0) {
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) {
+                const int s = colpiv[part + PARTS * i];
+                if (s >= 0) st_el(W, wide, int64_t(my_t) * npiv + s, ex[int(lg[a[i]]) + my_lead]);
+            }
+        }
+    } else {
+        if (tid == 0)
             for (int t = npiv; t < kPanel; ++t) out[int64_t(blockIdx.x) * kPanel + t] = -1;
-    }
-}
-
-// W = K^{-1}, K[s][t] = orig[r + rows[s]][cols[t]] (rp x rp), by Gauss-Jordan
-// on [K | I] without row exchanges: step t takes as pivot the first row not
-// yet used with a nonzero entry in column t, scales it to 1 there and clears
-// column t from every other row; the row that pivoted on column t ends as
-// row t of [I | K^{-1}].  W is written as elements, row pitch rp.
-// Thread (ty, tx) of the 8 x 128 block keeps column tx of rows 8ty..8ty+7
-// in registers.  Per step only column t (as logarithms) and the scaled
-// pivot row pass through LDS, double-buffered; every wave picks the pivot
-// itself from column t, so a step costs two barriers and no row is moved.
-constexpr int kInvThreads = 1024;
-
-template <bool LDS_TABS>
-__global__ __launch_bounds__(kInvThreads) void pivot_inverse_kernel(const uint16_t* orig, int64_t r,
-                                                                    const PanelState* st, int wide, void* W,
-                                                                    DevField F)
-{
-    constexpr int kCols = 2 * kPanel, kRowGroups = kInvThreads / kCols, RPT = kPanel / kRowGroups;
-    __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
-    __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
-    __shared__ __align__(16) uint32_t lcol[2][kPanel];  // logs of column t (2q for zeros)
-    __shared__ uint16_t prow[2][kCols];   // the scaled pivot row
-    __shared__ int pivot_of[kPanel];      // row that pivoted on column t
-    __shared__ int row_pos[kPanel];       // its inverse
-    const int rp = st->rp;
-    const int q = int(F.q);
-    const int tid = threadIdx.x, tx = tid % kCols, ty = tid / kCols;
-    if constexpr (LDS_TABS) {  // tables in LDS when they fit (e <= 10)
-        for (int k = tid; k <= 4 * q; k += kInvThreads) sexp[k] = F.exp[k];
-        for (int k = tid; k <= q; k += kInvThreads) slog[k] = F.log[k];
-    }
-    const uint16_t* ex = LDS_TABS ? sexp : F.exp;
-    const uint32_t* lg = LDS_TABS ? slog : F.log;
-    uint32_t v[RPT];  // v[k] = M[RPT * ty + k][tx]; zero outside the rp x 2rp matrix
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int s = RPT * ty + k;
-        v[k] = s >= rp || tx >= 2 * rp ? 0u
-               : tx < rp              ? uint32_t(orig[(r + st->rows[s]) * kPanel + st->cols[tx]])
-                                      : uint32_t(tx - rp == s ? 1 : 0);
-    }
-    bool used = false;  // lane s of every wave tracks row s
-    const int lane = tid & 63;
-    __syncthreads();
-    for (int t = 0; t < rp; ++t) {
-        const int b = t & 1;
-        if (tx == t) {
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) lcol[b][RPT * ty + k] = lg[v[k]];
-        }
-        __syncthreads();
-        // Every wave finds the same pivot: the first unused row with a
-        // nonzero entry in column t (K is invertible, so one exists).
-        const uint32_t lc = lcol[b][lane];
-        const uint64_t bal = __ballot(!used && lane < rp && lc != uint32_t(2 * q));
-        const int p = bal ? __ffsll(static_cast<long long>(bal)) - 1 : t;
-        used |= lane == p;
-        if (tid == 0) pivot_of[t] = p;
-        if (ty == p / RPT) {  // the pivot row's owners scale it and publish it
-            const int plinv = bal ? q - int(lcol[b][p]) : 2 * q;  // log of 1 / M[p][t]
-            const int kp = p % RPT;
-            uint32_t x = 0;
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) x = k == kp ? v[k] : x;
-            const uint32_t y = ex[plinv + int(lg[x])];
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) v[k] = k == kp ? y : v[k];
-            prow[b][tx] = uint16_t(y);
-        }
-        __syncthreads();
-        // M[s][tx] += M[s][t] * (pivot row)[tx] for s != p: the multipliers'
-        // logs are one contiguous run of lcol, all lookups independent
-        const int lp = int(lg[prow[b][tx]]);
-        uint32_t ls[RPT];
-        const uint4* lv = reinterpret_cast<const uint4*>(&lcol[b][RPT * ty]);
-#pragma unroll
-        for (int h = 0; h < RPT / 4; ++h) {
-            const uint4 w = lv[h];
-            ls[4 * h] = w.x;
-            ls[4 * h + 1] = w.y;
-            ls[4 * h + 2] = w.z;
-            ls[4 * h + 3] = w.w;
-        }
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const uint32_t l = RPT * ty + k == p ? uint32_t(2 * q) : ls[k];
-            v[k] ^= ex[int(l) + lp];
-        }
-    }
-    if (tid < rp) row_pos[pivot_of[tid]] = tid;
-    __syncthreads();
-    if (tx >= rp && tx < 2 * rp) {
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int s = RPT * ty + k;
-            if (s < rp) st_el(W, wide, int64_t(row_pos[s]) * rp + (tx - rp), v[k]);
-        }
     }
 }
 
@@ -468,54 +405,44 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     for (int64_t c0 = 0; c0 < n && r < m; c0 += kPanel) {
         const int bc = int(std::min<int64_t>(kPanel, n - c0));
         const int64_t mr = m - r;
-        auto launch_select = [&]<int ROWS>(int64_t nb, int64_t ncand, const int* in, int* out, int final) {
+        // A pivot-search launch; the final level (one workgroup) also writes
+        // the panel state and W = K^{-1}.
+        auto launch_select = [&]<int ROWS, bool FIN>(int64_t nb, int64_t ncand, const int* in, int* out) {
             const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * kSelParts)};
             if (lds_tabs)
-                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, true>), grid, block, 0, s, orig, r, bc, in,
-                                   ncand, out, final, st, F);
+                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, true, FIN>), grid, block, 0, s, orig, r, bc,
+                                   in, ncand, out, st, F, wide, static_cast<void*>(W));
             else
-                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, false>), grid, block, 0, s, orig, r, bc, in,
-                                   ncand, out, final, st, F);
+                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, false, FIN>), grid, block, 0, s, orig, r, bc,
+                                   in, ncand, out, st, F, wide, static_cast<void*>(W));
         };
         hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s, A->data, lda,
                            m, c0, bc, wide, orig);
         // Probe on the first rows; the whole tournament only when they lack a
         // pivot in some column and further rows exist.
         const int64_t probe = std::min<int64_t>(mr, kProbeRows);
-        auto launch_inverse = [&] {
-            if (lds_tabs)
-                hipLaunchKernelGGL(pivot_inverse_kernel<true>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide, W,
-                                   F);
-            else
-                hipLaunchKernelGGL(pivot_inverse_kernel<false>, dim3(1), dim3(kInvThreads), 0, s, orig, r, st, wide,
-                                   W, F);
-        };
-        launch_select.template operator()<kProbeRows>(1, probe, static_cast<const int*>(nullptr), cand[0], 1);
-        // The state goes to the host while the device already inverts the
-        // probe's pivot block (redone below if the tournament runs).
+        launch_select.template operator()<kProbeRows, true>(1, probe, static_cast<const int*>(nullptr), cand[0]);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(hsp, st, sizeof(PanelState), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipEventRecord(sel_done, s) != hipSuccess)
+            hipEventRecord(sel_done, s) != hipSuccess || hipEventSynchronize(sel_done) != hipSuccess)
             return GF2E_EDEVICE;
-        launch_inverse();
-        if (hipEventSynchronize(sel_done) != hipSuccess) return GF2E_EDEVICE;
         if (hs.rp < bc && mr > probe) {
-            // Tournament levels until one workgroup holds all candidates.
+            // Tournament levels of kSelRows-row workgroups until at most
+            // kProbeRows candidates remain, then the final level on those.
             const int* in = nullptr;
             int64_t ncand = mr;
-            for (int level = 0;; ++level) {
+            for (int level = 0; ncand > kProbeRows; ++level) {
                 const int64_t nb = ceil_div(ncand, kSelRows);
                 int* out = cand[level & 1];
-                launch_select.template operator()<kSelRows>(nb, ncand, in, out, nb == 1 ? 1 : 0);
-                if (nb == 1) break;
+                launch_select.template operator()<kSelRows, false>(nb, ncand, in, out);
                 in = out;
                 ncand = nb * kPanel;
             }
+            launch_select.template operator()<kProbeRows, true>(1, ncand, in, cand[0]);
             if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
             if (hipMemcpyAsync(hsp, st, sizeof(PanelState), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return GF2E_EDEVICE;
-            launch_inverse();
         }
         const int rp = hs.rp;
         if (rp == 0) continue;
