@@ -6,20 +6,24 @@
 // speed, recurses through PLE decomposition so that most of the work becomes
 // matrix products.  Here the matrix is processed in column panels of 64, and
 // per panel:
-//   1. pivots: a tournament over the rows r..m-1 of the panel.  Workgroups
-//      of 1024 rows eliminate their rows column by column in LDS and keep
-//      the rows that became pivots; the kept rows of all workgroups go
-//      through the same step again until one workgroup remains, whose pivots
-//      (rp of them, with their columns) are the panel's.
-//   2. W = K^{-1}, where K holds the original entries of the pivot rows at
-//      the pivot columns (one workgroup, Gauss-Jordan in LDS).
-//   3. the pivot rows are moved to rows r..r+rp-1, and on columns c0..n-1:
-//          X1 = W * A[pivot rows]                 (rows r..r+rp-1)
-//          A[rows below] += Z * X1                (Z: their original pivot-column entries)
-//          A[rows above] += Y * X1                (reduced form only)
-//      three products on the bitsliced path.  The rows below become zero on
-//      the panel (they lie in the span of the pivot rows there), and the
-//      pivot rows become the reduced rows.
+//   1. pivots and W = K^{-1} (K: the original entries of the pivot rows at
+//      the pivot columns).  A probe workgroup eliminates the first 128 of
+//      the rows r..m-1; when they give a pivot in every panel column, they
+//      are the panel's pivots.  Otherwise a tournament over all the rows
+//      keeps each workgroup's pivot rows until one workgroup holds them all.
+//      That last workgroup (or the probe) eliminates by Gauss-Jordan and
+//      carries each row along as a combination of the pivot rows, so it
+//      also writes W.
+//   2. the pivot rows are moved to rows r..r+rp-1 (only the rows that must
+//      move), and on columns c0..n-1 two products on the bitsliced path
+//      finish the panel:
+//          X1 = W * A[pivot rows]          (in place over the pivot rows)
+//          A[other rows] += G * X1         (G: their original pivot-column
+//                                           entries, zero on the pivot rows)
+//      where the other rows are those below, and those above as well for
+//      the reduced form.  The rows below become zero on the panel (they lie
+//      in the span of the pivot rows there), and the pivot rows become the
+//      reduced rows.
 // The reduced row echelon form is unique, so it equals the oracle's result
 // whatever rows are chosen as pivots.
 #include <hip/hip_runtime.h>
@@ -87,7 +91,6 @@ __global__ void panel_copy_kernel(const void* A, int64_t lda, int64_t m, int64_t
 
 // State of the pivot search of one panel.
 struct PanelState {
-    int next[kPanel + 1];  // candidate pivot row (relative to r) of column j, INT_MAX = none
     int rows[kPanel];      // pivot t: row (relative to r) ...
     int cols[kPanel];      // ... and panel column
     int rp;                // pivots found
@@ -102,7 +105,8 @@ struct PanelState {
 // valid pivot set with the panel's pivot columns.  Candidates are row
 // indices relative to r (in == nullptr: rows 0..ncand-1; -1: an empty slot).
 // A workgroup writes its kept rows to out[blockIdx.x*kPanel + t] (-1 past
-// its count); the last level (final) writes the panel state instead.
+// its count); the final level writes the panel state and W = K^{-1} instead
+// (see the Gauss-Jordan step below).
 //
 // Each row is held in registers by PARTS neighbouring lanes of one wave,
 // lane `part` owning columns part, part + PARTS, ...  The column loop is
