@@ -248,7 +248,10 @@ int gf2e_schedule(int e, uint32_t f, int* t, uint32_t* u, uint32_t* v, uint8_t* 
  *   A-side operand planes: t planes of K64p x Mp words, word (kw, r) = row r,
  *     k-bits [64kw, 64kw+64);
  *   B-side operand planes: t planes of K64p x Np words, word (kw, j) =
- *     column j, k-bits [64kw, 64kw+64);
+ *     column j, k-bits [64kw, 64kw+64) in B-side bit order: inside each
+ *     aligned group of four, bits 4g, 4g+1, 4g+2, 4g+3 hold k = 4g+2, 4g+1,
+ *     4g, 4g+3 (the first and third k trade places; the fp4 kernels then
+ *     expand both sides with four masks and one shift);
  *   product planes: t planes of Mp x (Np/64) words, row-major.
  * Mp, Np must be multiples of 256 and >= m, n; K64p = 4*ceil(k/256).
  * All plane pointers are device pointers owned by the caller. */

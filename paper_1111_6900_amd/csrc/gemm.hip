@@ -9,8 +9,10 @@
 // GF(2) product.  Only the parities are written back, bit-packed.
 //
 // The order of k inside a 64-bit step does not matter for the sum, only that
-// both operands use the same order: A and B chunks are expanded by the same
-// code and read with the same (lane group, byte) -> k assignment.
+// both operands use the same order.  B words come in B-side bit order (k-bits
+// 4g and 4g+2 of each group of four trade places, b_side_bit); every kernel
+// undoes that swap when it expands or stages B, so that A and B are read with
+// the same (lane group, byte) -> k assignment.
 //
 // VALU path: the same planes, AND/XOR on 32-bit words (acc ^= a & b, one
 // v_bitop3 per 32 bit-products), parity by popcount at the end.
@@ -26,14 +28,18 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Expanded chunk c (0..7) of a 128-bit k-step held in two words: 16 bytes,
-// byte (4*q + b) of the chunk = bit (8*b + 4*(c&1) + q) of 32-bit half c>>1.
+// byte (4*q + b) of the chunk = k-bit (8*b + 4*(c&1) + q) of 32-bit half
+// c>>1.  On the B side that k-bit sits at bit b_side_bit(q) of its nibble, so
+// dwords 0 and 2 take their bits from the other position (same cost).
+template <bool BSIDE>
 __device__ inline uint4 expand_chunk(uint64_t w0, uint64_t w1, int c)
 {
     const uint64_t w = (c < 4) ? w0 : w1;
     const uint32_t h = uint32_t(w >> (32 * ((c >> 1) & 1)));
     const uint32_t s = 4 * (c & 1);
     const uint32_t M = 0x01010101u;
-    return make_uint4((h >> s) & M, (h >> (s + 1)) & M, (h >> (s + 2)) & M, (h >> (s + 3)) & M);
+    constexpr int q0 = BSIDE ? 2 : 0, q2 = BSIDE ? 0 : 2;
+    return make_uint4((h >> (s + q0)) & M, (h >> (s + 1)) & M, (h >> (s + q2)) & M, (h >> (s + 3)) & M);
 }
 
 template <int BM, int BN, int WM, int WN>
@@ -90,8 +96,14 @@ __device__ __attribute__((always_inline)) inline void mfma_tile(const uint64_t* 
         for (int q = 0; q < RPT; ++q) {
             const int r = tid + q * NT;
             if (r < TL::kRows) {
+                // BM and NT are multiples of 64: the side is uniform in a wave
+                if (__builtin_amdgcn_readfirstlane(r) < BM) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) lds[st][c][r] = expand_chunk(stg[q][0], stg[q][1], c);
+                    for (int c = 0; c < 8; ++c) lds[st][c][r] = expand_chunk<false>(stg[q][0], stg[q][1], c);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) lds[st][c][r] = expand_chunk<true>(stg[q][0], stg[q][1], c);
+                }
             }
         }
     };
@@ -218,17 +230,17 @@ __device__ inline v8i fp4_operand(const uint4& x)
 // chunk h as nibble j; e2m1 codes 0b0001, 0b0010 and 0b0100 are 0.5, 1.0 and
 // 2.0.  The A side gives dwords q = 0..3 the values 0.5, 1, 2, 2 and the B
 // side 2, 1, 0.5, 0.5, so the product of two set bits is exactly 1.0 for
-// every q and the f32 accumulator counts common ones.  On the A side bit q of
-// a nibble already is the code of its value for q < 3, so its expansion is
-// mostly masks.
+// every q and the f32 accumulator counts common ones.  Bit q of an A nibble
+// already is the code of its value for q < 3.  B words hold k-bit q of a
+// nibble at bit b_side_bit(q) (positions 2, 1, 0, 3), which again is the code
+// of its value for q < 3: each side takes four masks and one shift.
 template <bool BSIDE>
 __device__ __attribute__((always_inline)) inline uint4 expand_fp4(uint32_t h)
 {
     if constexpr (!BSIDE)
         return make_uint4(h & 0x11111111u, h & 0x22222222u, h & 0x44444444u, (h >> 1) & 0x44444444u);
     else
-        return make_uint4((h << 2) & 0x44444444u, h & 0x22222222u, (h >> 2) & 0x11111111u,
-                          (h >> 3) & 0x11111111u);
+        return make_uint4(h & 0x44444444u, h & 0x22222222u, h & 0x11111111u, (h >> 3) & 0x11111111u);
 }
 
 // Split form of a chunk: dwords 0..2 of the expansion use disjoint bits and
@@ -643,7 +655,14 @@ __global__ __launch_bounds__(256) void gemm_valu_kernel(
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[r][c] = 0;
 
-    uint64_t w0 = src[0], w1 = src[ld];
+    // A words are staged in B-side bit order (k-bits 4g and 4g+2 swapped), so
+    // both operands of the AND hold the same k at each bit.
+    const uint64_t swap_mask = isA ? 0x1111111111111111ull : 0ull;
+    auto to_b_order = [&](uint64_t x) {
+        const uint64_t d = ((x >> 2) ^ x) & swap_mask;
+        return x ^ (d | (d << 2));
+    };
+    uint64_t w0 = to_b_order(src[0]), w1 = to_b_order(src[ld]);
     auto store = [&](int st) {
         lds[st][0][slot] = uint32_t(w0);
         lds[st][1][slot] = uint32_t(w0 >> 32);
@@ -656,8 +675,8 @@ __global__ __launch_bounds__(256) void gemm_valu_kernel(
         const int st = kb & 1;
         const bool more = kb + 1 < K128;
         if (more) {
-            w0 = src[int64_t(2 * kb + 2) * ld];
-            w1 = src[int64_t(2 * kb + 3) * ld];
+            w0 = to_b_order(src[int64_t(2 * kb + 2) * ld]);
+            w1 = to_b_order(src[int64_t(2 * kb + 3) * ld]);
         }
 #pragma unroll
         for (int kd = 0; kd < 4; ++kd) {

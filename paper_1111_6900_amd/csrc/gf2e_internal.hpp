@@ -7,6 +7,8 @@
 //       base + s*K64p*Mp + kw*Mp + r      -- row r of A, k-bits [64kw, 64kw+64)
 //   operand planes (B side):  plane s of T, word (kw, j) at
 //       base + s*K64p*Np + kw*Np + j      -- column j of B, k-bits [64kw, 64kw+64)
+//       in B-side bit order: inside every aligned group of four k, bits
+//       4g, 4g+1, 4g+2, 4g+3 hold k = 4g+2, 4g+1, 4g, 4g+3 (b_side_bit)
 //   product planes:           plane s of T, word (i, w) at
 //       base + s*Mp*ldp + i*ldp + w       -- row i, columns [64w, 64w+64), ldp = Np/64
 //
@@ -25,6 +27,12 @@ constexpr int kRowAlign = 256;  // padding of plane rows (largest product tile)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+// B-side bit order: the bit of a B-side word that holds k-bit k of its
+// 64-bit step (an involution that swaps the first and third k of each group
+// of four).  With it the fp4 kernels expand a B chunk with the same four
+// masks and one shift as an A chunk; the other kernels read B in this order.
+constexpr int b_side_bit(int k) { return (k & 1) ? k : (k ^ 2); }
+
 // k is padded to whole 256-bit steps, so every product kernel's stages are
 // full and its loads need no bounds guard.
 inline int64_t kwords_padded(int64_t k) { return 4 * ceil_div(k, 256); }

@@ -172,9 +172,10 @@ __device__ __attribute__((always_inline)) inline void load_col_planes_tile(const
     __syncthreads();
     uint64_t lo[8] = {}, hi[8] = {};
     bool bad = false;
+    // bit c of the column word takes k-row b_side_bit(c) of the tile
 #pragma unroll
     for (int c = 0; c < 64; ++c) {
-        const uint32_t x = reinterpret_cast<const elem_t*>(tile[c])[lane];
+        const uint32_t x = reinterpret_cast<const elem_t*>(tile[b_side_bit(c)])[lane];
         bad |= (x >> E) != 0;
         lo[c >> 3] |= uint64_t(x & 0xFFu) << (8 * (c & 7));
         if constexpr (E > 8) hi[c >> 3] |= uint64_t(x >> 8) << (8 * (c & 7));

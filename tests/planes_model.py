@@ -41,18 +41,35 @@ def operand_planes_a(A, e, u, Mp, K64p):
     return out
 
 
+def b_side_order(words):
+    """Swap bits 4g and 4g+2 of every word (the B-side bit order of the
+    layout: bits 4g..4g+3 hold k = 4g+2, 4g+1, 4g, 4g+3).  The swap is its
+    own inverse, so it also turns B-side words back into k order."""
+    w = np.asarray(words, dtype=np.uint64)
+    out = w.copy()
+    for g in range(16):
+        lo, hi = np.uint64(4 * g), np.uint64(4 * g + 2)
+        b0 = (w >> lo) & np.uint64(1)
+        b2 = (w >> hi) & np.uint64(1)
+        out &= ~((np.uint64(1) << lo) | (np.uint64(1) << hi))
+        out |= (b0 << hi) | (b2 << lo)
+    return out
+
+
 def operand_planes_b(B, e, v, Np, K64p):
-    """Expected B-side planes (columns of B along k): (t, K64p, Np)."""
-    return operand_planes_a(np.asarray(B).T, e, v, Np, K64p)
+    """Expected B-side planes (columns of B along k, B-side bit order):
+    (t, K64p, Np)."""
+    return b_side_order(operand_planes_a(np.asarray(B).T, e, v, Np, K64p))
 
 
 def gf2_products(Ap, Bp, m, n):
-    """P_s = Ahat_s Bhat_s^T mod 2 from plane arrays (t, K64p, rows)."""
+    """P_s = Ahat_s Bhat_s^T mod 2 from plane arrays (t, K64p, rows); B-side
+    words are read in B-side bit order."""
     t, K64p, _ = Ap.shape
     out = []
     for s in range(t):
         a = unpack_rows(np.ascontiguousarray(Ap[s, :, :m].T), K64p * 64)
-        b = unpack_rows(np.ascontiguousarray(Bp[s, :, :n].T), K64p * 64)
+        b = unpack_rows(np.ascontiguousarray(b_side_order(Bp[s, :, :n]).T), K64p * 64)
         out.append((a @ b.T) & 1)
     return out
 

@@ -170,3 +170,15 @@ def test_null_context_is_rejected():
     assert L.gf2e_sync(None, None) == g.EINVAL
     assert L.gf2e_profile(None, 1) == g.EINVAL
     assert L.gf2e_workspace_bytes(None) == 0
+
+
+def test_b_side_bit_order_model():
+    """The test model of the B-side bit order: k-bits 4g and 4g+2 of each
+    group of four trade places, the others stay, and the swap undoes itself."""
+    import numpy as np
+    from tests import planes_model as pm
+    for k in range(64):
+        want = k if k % 2 else k ^ 2
+        assert int(pm.b_side_order(np.uint64(1) << np.uint64(k))) == 1 << want, k
+    w = np.random.default_rng(5).integers(0, 2**64, size=100, dtype=np.uint64)
+    assert (pm.b_side_order(pm.b_side_order(w)) == w).all()

@@ -83,7 +83,7 @@ def test_slice_figure1(g, ctx, golden_dir):
         assert got == meta[f"slice{i}"], (i, got)
 
 
-@pytest.mark.parametrize("kind", list(range(8)))
+@pytest.mark.parametrize("kind", list(range(9)))
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 200, 33), (64, 128, 64), (130, 384, 250),
                                    (256, 64, 512), (513, 1000, 300)])
 def test_plane_products(g, ctx, kind, shape):
