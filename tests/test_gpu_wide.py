@@ -53,7 +53,7 @@ def test_products(g, e, f, form, shape):
     c.close()
 
 
-@pytest.mark.parametrize("kind", list(range(8)))
+@pytest.mark.parametrize("kind", list(range(9)))
 @pytest.mark.parametrize("e", [11, 16])
 def test_every_kernel(g, e, kind):
     f = workload.WIDE_POLY[e]
