@@ -119,7 +119,8 @@ struct PanelState {
 // panel (the usual case for a matrix of full rank), no other row can add
 // one, and their pivots are the panel's.
 constexpr int kSelRows = 256;   // rows per workgroup of the tournament
-constexpr int kSelParts = 4;    // lanes per row
+constexpr int kSelParts = 4;    // lanes per row in the tournament levels
+constexpr int kFinalParts = 8;  // lanes per row in the final level (128 rows, 1024 threads)
 constexpr int kProbeRows = 128; // rows of the probe (2 kPanel: full rank unless the rows are special)
 
 template <int ROWS, int PARTS, bool LDS_TABS, bool FINAL>
@@ -220,10 +221,9 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
             if (part + PARTS * i > J) v[i] ^= ex[lf + plog[part + PARTS * i]];
-            if constexpr (FINAL) {
-                const uint32_t d = ex[lf + alog[part + PARTS * i]];
-                a[i] = part + PARTS * i <= J ? a[i] ^ d : a[i];
-            }
+            // combinations only reach the columns of pivots found so far
+            if constexpr (FINAL)
+                if (part + PARTS * i <= J) a[i] ^= ex[lf + alog[part + PARTS * i]];
         }
         if constexpr (J + 1 < kPanel) offer(J + 1, v[(J + 1) / PARTS] != 0);
     };
@@ -412,12 +412,13 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         // A pivot-search launch; the final level (one workgroup) also writes
         // the panel state and W = K^{-1}.
         auto launch_select = [&]<int ROWS, bool FIN>(int64_t nb, int64_t ncand, const int* in, int* out) {
-            const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * kSelParts)};
+            constexpr int PARTS = FIN ? kFinalParts : kSelParts;
+            const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * PARTS)};
             if (lds_tabs)
-                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, true, FIN>), grid, block, 0, s, orig, r, bc,
+                hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, true, FIN>), grid, block, 0, s, orig, r, bc,
                                    in, ncand, out, st, F, wide, static_cast<void*>(W));
             else
-                hipLaunchKernelGGL((panel_select_kernel<ROWS, kSelParts, false, FIN>), grid, block, 0, s, orig, r, bc,
+                hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, false, FIN>), grid, block, 0, s, orig, r, bc,
                                    in, ncand, out, st, F, wide, static_cast<void*>(W));
         };
         hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s, A->data, lda,
