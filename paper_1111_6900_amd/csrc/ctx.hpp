@@ -130,8 +130,9 @@ struct Ctx {
     // and log[q + 1] (uint32, log 0 = 2q), so that exp[log a + log b] = a*b.
     std::map<uint64_t, void*> ftabs;
     DevTables field_tables(int e, uint32_t f);  // {nullptr, nullptr} on failure
-    // Pinned host buffer for small device-to-host reads (the pivot state of
-    // an echelon panel), so that they are truly asynchronous.
+    // Mapped, coherent host buffer that the final pivot-search kernel of an
+    // echelon panel writes its state into; the host reads it once the launch
+    // has completed (no copy launch in between).
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
     void* ensure_pinned(size_t bytes);

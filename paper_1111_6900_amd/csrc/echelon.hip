@@ -126,7 +126,8 @@ constexpr int kProbeRows = 128; // rows of the probe (2 kPanel: full rank unless
 template <int ROWS, int PARTS, bool LDS_TABS, bool FINAL>
 __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16_t* orig, int64_t r, int bc,
                                                                     const int* in, int64_t ncand, int* out,
-                                                                    PanelState* st, DevField F, int wide, void* W)
+                                                                    PanelState* st, PanelState* hst, DevField F,
+                                                                    int wide, void* W)
 {
     constexpr int NT = ROWS * PARTS, CPT = kPanel / PARTS;
     static_assert(kPanel % PARTS == 0 && 64 % PARTS == 0 && NT <= 1024, "rows lie within one wave");
@@ -201,6 +202,8 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
                 if constexpr (FINAL) {
                     st->rows[npiv] = row;
                     st->cols[npiv] = J;
+                    hst->rows[npiv] = row;
+                    hst->cols[npiv] = J;
                 } else {
                     out[int64_t(blockIdx.x) * kPanel + npiv] = row;
                 }
@@ -231,7 +234,10 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
         (step.template operator()<J>(), ...);
     }(std::make_integer_sequence<int, kPanel>{});
     if constexpr (FINAL) {
-        if (tid == 0) st->rp = npiv;
+        if (tid == 0) {
+            st->rp = npiv;
+            hst->rp = npiv;
+        }
         // W[t][s] = coefficient of pivot row s in pivot row t, over its pivot
         if (my_t >= 0) {
 #pragma unroll
@@ -337,7 +343,7 @@ void* Ctx::ensure_pinned(size_t bytes)
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     pinned_bytes = 0;
-    if (hipHostMalloc(&pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&pinned, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         (void)hipGetLastError();
         pinned = nullptr;
         return nullptr;
@@ -390,8 +396,14 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     uint8_t* G = W + b_w;
     uint8_t* mvbuf = G + b_g;
 
+    // The final pivot-search level writes the panel state to device memory
+    // (read by later kernels) and to this mapped host copy (read by the host
+    // once the launch has completed), so no copy runs between them.
     PanelState* hsp = static_cast<PanelState*>(ensure_pinned(sizeof(PanelState)));
     if (!hsp) return GF2E_ENOMEM;
+    PanelState* hst_dev = nullptr;
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&hst_dev), hsp, 0) != hipSuccess || !hst_dev)
+        return GF2E_EDEVICE;
     hipEvent_t sel_done = get_event();
     if (!sel_done) return GF2E_EDEVICE;
     struct EventBack {  // back to the pool on every return
@@ -416,10 +428,10 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * PARTS)};
             if (lds_tabs)
                 hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, true, FIN>), grid, block, 0, s, orig, r, bc,
-                                   in, ncand, out, st, F, wide, static_cast<void*>(W));
+                                   in, ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
             else
                 hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, false, FIN>), grid, block, 0, s, orig, r, bc,
-                                   in, ncand, out, st, F, wide, static_cast<void*>(W));
+                                   in, ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
         };
         hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s, A->data, lda,
                            m, c0, bc, wide, orig);
@@ -428,7 +440,6 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         const int64_t probe = std::min<int64_t>(mr, kProbeRows);
         launch_select.template operator()<kProbeRows, true>(1, probe, static_cast<const int*>(nullptr), cand[0]);
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(hsp, st, sizeof(PanelState), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipEventRecord(sel_done, s) != hipSuccess || hipEventSynchronize(sel_done) != hipSuccess)
             return GF2E_EDEVICE;
         if (hs.rp < bc && mr > probe) {
@@ -445,8 +456,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             }
             launch_select.template operator()<kProbeRows, true>(1, ncand, in, cand[0]);
             if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-            if (hipMemcpyAsync(hsp, st, sizeof(PanelState), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
+            if (hipStreamSynchronize(s) != hipSuccess)
                 return GF2E_EDEVICE;
         }
         const int rp = hs.rp;
