@@ -253,11 +253,11 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
 }
 
 // G[i][t] = original entry of (new) row i at pivot column t, for all rows:
-// rows i < r are unmoved, row r + k is old row r + perm[k], and the pivot
-// rows r..r+rp-1 get zeros (so that one product can update every other row).
-// Pitch rp.
+// rows i < r are unmoved, row r + k is old row r + perm[k] for k < plen and
+// unmoved beyond, and the pivot rows r..r+rp-1 get zeros (so that one
+// product can update every other row).  Pitch rp.
 __global__ void gather_pivot_columns_kernel(const uint16_t* orig, int64_t r, int64_t m, const int* perm,
-                                            const PanelState* st, int rp, int wide, void* G)
+                                            int plen, const PanelState* st, int rp, int wide, void* G)
 {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= m * rp) return;
@@ -267,7 +267,7 @@ __global__ void gather_pivot_columns_kernel(const uint16_t* orig, int64_t r, int
         st_el(G, wide, idx, 0);
         return;
     }
-    const int64_t src = i < r ? i : r + perm[i - r];
+    const int64_t src = i < r ? i : r + (i - r < plen ? perm[i - r] : i - r);
     st_el(G, wide, idx, orig[src * kPanel + st->cols[t]]);
 }
 
@@ -398,9 +398,13 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
 
     // The final pivot-search level writes the panel state to device memory
     // (read by later kernels) and to this mapped host copy (read by the host
-    // once the launch has completed), so no copy runs between them.
-    PanelState* hsp = static_cast<PanelState*>(ensure_pinned(sizeof(PanelState)));
-    if (!hsp) return GF2E_ENOMEM;
+    // once the launch has completed), so no copy runs between them.  The
+    // row permutation is staged after it in the same pinned buffer.
+    constexpr size_t kPermAt = (sizeof(PanelState) + 255) / 256 * 256;
+    uint8_t* pin = static_cast<uint8_t*>(ensure_pinned(kPermAt + size_t(m + 2 * kPanel) * 4));
+    if (!pin) return GF2E_ENOMEM;
+    PanelState* hsp = reinterpret_cast<PanelState*>(pin);
+    int* hperm = reinterpret_cast<int*>(pin + kPermAt);
     PanelState* hst_dev = nullptr;
     if (hipHostGetDevicePointer(reinterpret_cast<void**>(&hst_dev), hsp, 0) != hipSuccess || !hst_dev)
         return GF2E_EDEVICE;
@@ -412,7 +416,6 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         ~EventBack() { c->event_pool.push_back(ev); }
     } event_back{this, sel_done};
     const PanelState& hs = *hsp;
-    std::vector<int> hperm;
     std::vector<char> is_piv;
     uint8_t* Ad = static_cast<uint8_t*>(A->data);
     const int64_t lda = A->ld;
@@ -467,16 +470,19 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         // Rows r..r+rp-1 receive the pivot rows; a non-pivot row found there
         // moves to the place left by a pivot row from further down.  The
         // order of the non-pivot rows does not matter: they are reduced by
-        // later panels, and the reduced form is unique.
-        hperm.resize(size_t(mr) + 2 * kPanel);
-        for (int64_t i = 0; i < mr; ++i) hperm[i] = int(i);
+        // later panels, and the reduced form is unique.  Rows from plen on
+        // (past every pivot row) stay where they are, so only the first plen
+        // entries of the permutation and the list of moved rows are sent.
+        int plen = rp;
+        for (int t = 0; t < rp; ++t) plen = std::max(plen, hs.rows[t] + 1);
+        for (int i = 0; i < plen; ++i) hperm[i] = i;
         is_piv.assign(size_t(std::min<int64_t>(mr, kPanel)), 0);
         for (int t = 0; t < rp; ++t)
             if (hs.rows[t] < rp) is_piv[hs.rows[t]] = 1;
         int disp[kPanel], nd = 0;
         for (int k = 0; k < rp; ++k)
             if (!is_piv[k]) disp[nd++] = k;
-        int* moves = hperm.data() + mr;
+        int* moves = hperm + plen;
         int nm = 0;
         for (int t = 0, j = 0; t < rp; ++t) {
             if (hs.rows[t] != t) moves[nm++] = t;
@@ -486,17 +492,19 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             }
         }
         for (int t = 0; t < rp; ++t) hperm[t] = hs.rows[t];
-        if (hipMemcpyAsync(perm, hperm.data(), size_t(mr + nm) * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        // from pinned memory: a direct copy; the host writes the buffer again
+        // only after the next panel's pivot search, which follows this copy
+        if (hipMemcpyAsync(perm, hperm, size_t(plen + nm) * 4, hipMemcpyHostToDevice, s) != hipSuccess)
             return GF2E_EDEVICE;
 
         hipLaunchKernelGGL(gather_pivot_columns_kernel, dim3(unsigned(ceil_div(m * rp, 256))), dim3(256), 0, s, orig,
-                           r, m, perm, st, rp, wide, G);
+                           r, m, perm, plen, st, rp, wide, G);
         const int64_t nc = n - c0;
         if (nm > 0) {
             hipLaunchKernelGGL(gather_rows_kernel, rows_grid(nm, nc), dim3(256), 0, s, A->data, lda, r, c0, perm,
-                               perm + mr, nm, nc, wide, mvbuf);
+                               perm + plen, nm, nc, wide, mvbuf);
             hipLaunchKernelGGL(scatter_rows_kernel, rows_grid(nm, nc), dim3(256), 0, s, A->data, lda, r, c0,
-                               perm + mr, nm, nc, wide, mvbuf);
+                               perm + plen, nm, nc, wide, mvbuf);
         }
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
 
