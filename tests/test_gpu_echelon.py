@@ -141,3 +141,30 @@ def test_rref_pivots_beyond_the_first_rows(ctx, e, f):
         Eo, ro, po = oracle.echelon(M, e, f)
         assert r == ro and piv == list(po)
         assert (E == Eo).all()
+
+
+@pytest.mark.parametrize("m,e", [(4096, 2), (8192, 8)])
+def test_rref_full_size_properties(g, m, e):
+    """The benchmark's echelon inputs at full size (too large for the oracle's
+    elimination), checked by properties that hold at any size: R is in
+    reduced row echelon form (increasing pivots, unit pivot columns, zeros
+    left of each pivot and below the rank), and sampled rows of A lie in the
+    row space of R, a_i = sum_t a_i[pivot t] * R_t, with that product taken
+    by the oracle."""
+    f = workload.DEFAULT_POLY[e]
+    print(f"rref full size m={m} e={e}", flush=True)
+    A = workload.field_matrix(np.random.default_rng(90000 + m + e), m, m, e)
+    c = g.Context(0, autotune=True)
+    Ad = dev(A, e)
+    r, piv = c.echelonize(Ad, e, f)
+    R = Ad.cpu().numpy()  # uint8 elements
+    c.close()
+    piv = np.asarray(piv, dtype=np.int64)
+    assert r >= m - 2 and len(piv) == r and (np.diff(piv) > 0).all()
+    assert not R[r:].any()
+    assert (R[:r][:, piv] == np.eye(r, dtype=R.dtype)).all()
+    left = np.arange(m)[None, :] < piv[:, None]
+    assert not (R[:r] * left).any()
+    rows = np.random.default_rng(m + e).choice(m, 8, replace=False)
+    coeff = A[rows][:, piv]
+    assert (oracle.matmul(coeff, R[:r], e, f).astype(np.int64) == A[rows]).all()
