@@ -38,7 +38,8 @@ struct BatchGraph {
     int* d_counters = nullptr;
     int n_items[kNumClasses] = {};
     int grid[kNumClasses] = {};
-    int max_slice_blocks = 0, max_combine_blocks = 0;
+    int* d_jobs = nullptr;  // job lists of the slicing and combining launches
+    JobList slice_jobs[2], combine_jobs[2];
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -49,6 +50,7 @@ struct BatchGraph {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
         if (d_counters) (void)hipFree(d_counters);
+        if (d_jobs) (void)hipFree(d_jobs);
         if (d_items) (void)hipFree(d_items);
         if (d_prods) (void)hipFree(d_prods);
         if (arena) (void)hipFree(arena);
@@ -105,8 +107,6 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
         offs.push_back(total);
         if (k > 0) total += align256(pl.a_bytes) + align256(pl.b_bytes) + align256(pl.p_bytes);
         prods.push_back(d);
-        bg->max_slice_blocks = std::max(bg->max_slice_blocks, d.slice_a_blocks + d.slice_b_blocks);
-        bg->max_combine_blocks = std::max(bg->max_combine_blocks, d.combine_blocks);
     }
     bg->count = int(prods.size());
     if (bg->count > 65535) return GF2E_EINVAL;
@@ -179,18 +179,59 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
                       hipMemcpyHostToDevice) != hipSuccess)
             return GF2E_EDEVICE;
 
+    // Job lists of the slicing and combining launches, per e-range: the
+    // products of the range and the prefix sums of their blocks, laid out as
+    // four lists of (first[n + 1], owner[n]) in one device array.
+    {
+        std::vector<int> host;
+        int64_t at[4] = {}, totals[4] = {};
+        int ns[4] = {};
+        for (int list = 0; list < 4; ++list) {
+            const bool combine = list >= 2, large = list & 1;
+            std::vector<int> own;
+            std::vector<int64_t> first{0};
+            for (size_t i = 0; i < prods.size(); ++i) {
+                const BatchProduct& d = prods[i];
+                if ((d.e > kBatchSmallE) != large) continue;
+                const int64_t blocks = combine ? d.combine_blocks : int64_t(d.slice_a_blocks) + d.slice_b_blocks;
+                if (blocks == 0) continue;
+                own.push_back(int(i));
+                first.push_back(first.back() + blocks);
+            }
+            if (first.back() > INT32_MAX) return GF2E_EINVAL;  // one launch's grid
+            at[list] = int64_t(host.size());
+            for (int64_t v : first) host.push_back(int(v));
+            host.insert(host.end(), own.begin(), own.end());
+            ns[list] = int(own.size());
+            totals[list] = first.back();
+        }
+        if (hipMalloc(&bg->d_jobs, host.size() * sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            return GF2E_ENOMEM;
+        }
+        if (hipMemcpy(bg->d_jobs, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            return GF2E_EDEVICE;
+        for (int list = 0; list < 4; ++list) {
+            JobList& jl = list >= 2 ? bg->combine_jobs[list & 1] : bg->slice_jobs[list & 1];
+            jl.first = bg->d_jobs + at[list];
+            jl.owner = bg->d_jobs + at[list] + ns[list] + 1;
+            jl.n = ns[list];
+            jl.total = int(totals[list]);
+        }
+    }
+
     // Capture: reset counters, grouped slicing, the persistent products of
     // each size class, grouped combining.
     if (hipStreamCreateWithFlags(&bg->cap, hipStreamNonBlocking) != hipSuccess) return GF2E_EDEVICE;
     if (hipStreamBeginCapture(bg->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return GF2E_EDEVICE;
     hipError_t err = launch_reset_counters(bg->d_counters, kNumClasses, bg->cap);
     if (err == hipSuccess)
-        err = launch_batched_slice(bg->d_prods, bg->count, bg->max_slice_blocks, c->d_err, bg->cap);
+        err = launch_batched_slice(bg->d_prods, bg->slice_jobs, c->d_err, bg->cap);
     for (int cls = 0; cls < kNumClasses && err == hipSuccess; ++cls)
         err = launch_persistent_gemm(kClassKinds[cls], bg->d_prods, bg->d_items + item_off[cls],
                                      bg->n_items[cls], bg->d_counters + cls, bg->grid[cls], bg->cap);
     if (err == hipSuccess)
-        err = launch_batched_combine(bg->d_prods, bg->count, bg->max_combine_blocks, bg->cap);
+        err = launch_batched_combine(bg->d_prods, bg->combine_jobs, bg->cap);
     hipGraph_t graph = nullptr;
     const hipError_t end = hipStreamEndCapture(bg->cap, &graph);
     bg->graph = graph;

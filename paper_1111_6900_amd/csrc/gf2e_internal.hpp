@@ -111,10 +111,20 @@ struct WorkItem {
 // item within this many k-words in all (at least one plane).
 constexpr int64_t kItemKWords = 256;
 
-hipError_t launch_batched_slice(const BatchProduct* prods, int count, int max_blocks, int* err,
-                                hipStream_t s);
-hipError_t launch_batched_combine(const BatchProduct* prods, int count, int max_blocks,
-                                  hipStream_t s);
+// The batched slicing and combining kernels are instantiated for two ranges
+// of e (up to kBatchSmallE, and above), each launched over its own products.
+constexpr int kBatchSmallE = 10;
+
+// A flattened launch over the products of one e-range: block b belongs to
+// product owner[i] when first[i] <= b < first[i + 1] (device arrays; first
+// has n + 1 entries, first[n] = total blocks).
+struct JobList {
+    const int* first = nullptr;
+    const int* owner = nullptr;
+    int n = 0, total = 0;
+};
+hipError_t launch_batched_slice(const BatchProduct* prods, const JobList (&jobs)[2], int* err, hipStream_t s);
+hipError_t launch_batched_combine(const BatchProduct* prods, const JobList (&jobs)[2], hipStream_t s);
 int batch_threads_per_block();
 // Persistent grouped products: workgroups take items in order from *counter
 // until it passes nitems.  kind: GEMM_MFMA_256x256_W8 or GEMM_MFMA_128x128.

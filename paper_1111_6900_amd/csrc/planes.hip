@@ -452,15 +452,31 @@ inline bool with_any_schedule(int e, int sid, Fn&& fn)
 // The batched kernels are instantiated for two ranges of e, so that the
 // large fields do not raise the register use of the kernels that serve the
 // common small ones; each launch skips the products outside its range.
-constexpr int kSmallE = 10;
+constexpr int kSmallE = kBatchSmallE;
+
+// Index i with first[i] <= b < first[i + 1] (b is uniform in the block, so
+// the search runs on scalar loads).
+__device__ inline int job_owner(const int* __restrict__ first, int n, int b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 template <int EMIN, int EMAX>
 __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProduct* __restrict__ prods,
+                                                                 const int* __restrict__ first,
+                                                                 const int* __restrict__ owner, int nprod,
                                                                  int* __restrict__ err)
 {
-    const BatchProduct& P = prods[blockIdx.y];
+    const int b = int(blockIdx.x), i = job_owner(first, nprod, b);
+    const BatchProduct& P = prods[owner[i]];
     if (P.e < EMIN || P.e > EMAX) return;
-    int64_t job = blockIdx.x;
+    int64_t job = b - first[i];
     if (job < P.slice_a_blocks) {
         const int64_t rb_count = P.Mp / kThreads;
         const int64_t r = (job % rb_count) * kThreads + threadIdx.x, kw = job / rb_count;
@@ -486,13 +502,15 @@ __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProd
 }
 
 template <int EMIN, int EMAX>
-__global__ __launch_bounds__(kThreads) void batched_combine_kernel(const BatchProduct* __restrict__ prods)
+__global__ __launch_bounds__(kThreads) void batched_combine_kernel(const BatchProduct* __restrict__ prods,
+                                                                   const int* __restrict__ first,
+                                                                   const int* __restrict__ owner, int nprod)
 {
-    const BatchProduct& P = prods[blockIdx.y];
+    const int b = int(blockIdx.x), j = job_owner(first, nprod, b);
+    const BatchProduct& P = prods[owner[j]];
     if (P.e < EMIN || P.e > EMAX) return;
-    if (int64_t(blockIdx.x) >= P.combine_blocks) return;
     const int64_t nw = (P.n + 63) / 64;
-    const int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t idx = int64_t(b - first[j]) * kThreads + threadIdx.x;
     if (idx >= P.m * nw) return;
     const int64_t i = idx / nw, w = idx % nw;
     with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
@@ -610,22 +628,27 @@ hipError_t launch_zero(void* C, int64_t rows, int64_t cols, int64_t ld, int elem
 
 namespace gf2e {
 
-hipError_t launch_batched_slice(const BatchProduct* prods, int count, int max_blocks, int* err,
-                                hipStream_t s)
+// One block per job of the products in each e-range (no idle blocks: a grid
+// of the largest product's jobs times the product count was mostly empty).
+hipError_t launch_batched_slice(const BatchProduct* prods, const JobList (&jobs)[2], int* err, hipStream_t s)
 {
-    if (count <= 0 || max_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((batched_slice_kernel<2, kSmallE>), dim3(max_blocks, count), dim3(kThreads), 0, s, prods, err);
-    hipLaunchKernelGGL((batched_slice_kernel<kSmallE + 1, kMaxE>), dim3(max_blocks, count), dim3(kThreads), 0, s,
-                       prods, err);
+    if (jobs[0].total > 0)
+        hipLaunchKernelGGL((batched_slice_kernel<2, kSmallE>), dim3(unsigned(jobs[0].total)), dim3(kThreads), 0, s,
+                           prods, jobs[0].first, jobs[0].owner, jobs[0].n, err);
+    if (jobs[1].total > 0)
+        hipLaunchKernelGGL((batched_slice_kernel<kSmallE + 1, kMaxE>), dim3(unsigned(jobs[1].total)), dim3(kThreads),
+                           0, s, prods, jobs[1].first, jobs[1].owner, jobs[1].n, err);
     return hipGetLastError();
 }
 
-hipError_t launch_batched_combine(const BatchProduct* prods, int count, int max_blocks, hipStream_t s)
+hipError_t launch_batched_combine(const BatchProduct* prods, const JobList (&jobs)[2], hipStream_t s)
 {
-    if (count <= 0 || max_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((batched_combine_kernel<2, kSmallE>), dim3(max_blocks, count), dim3(kThreads), 0, s, prods);
-    hipLaunchKernelGGL((batched_combine_kernel<kSmallE + 1, kMaxE>), dim3(max_blocks, count), dim3(kThreads), 0, s,
-                       prods);
+    if (jobs[0].total > 0)
+        hipLaunchKernelGGL((batched_combine_kernel<2, kSmallE>), dim3(unsigned(jobs[0].total)), dim3(kThreads), 0, s,
+                           prods, jobs[0].first, jobs[0].owner, jobs[0].n);
+    if (jobs[1].total > 0)
+        hipLaunchKernelGGL((batched_combine_kernel<kSmallE + 1, kMaxE>), dim3(unsigned(jobs[1].total)),
+                           dim3(kThreads), 0, s, prods, jobs[1].first, jobs[1].owner, jobs[1].n);
     return hipGetLastError();
 }
 
