@@ -16,7 +16,9 @@
 // four, so the product kernels step through whole 256-bit stages; products of
 // the plain path with k <= 128 use K64p = 2 and the one kernel with 128-bit
 // stages).  Padding bits are written as zero by the slicing kernels, so padded
-// k contributes nothing.
+// k contributes nothing; the batched slicer leaves the padding rows (and
+// columns) of its planes unwritten, since they only reach product rows and
+// columns that are never combined.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>

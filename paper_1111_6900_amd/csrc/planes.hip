@@ -477,9 +477,13 @@ __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProd
     const BatchProduct& P = prods[owner[i]];
     if (P.e < EMIN || P.e > EMAX) return;
     int64_t job = b - first[i];
+    // Rows past m and columns past n are not written: they only feed product
+    // rows and columns that the combine never reads (the padding of k, which
+    // enters every product, is written as zeros).
     if (job < P.slice_a_blocks) {
         const int64_t rb_count = P.Mp / kThreads;
         const int64_t r = (job % rb_count) * kThreads + threadIdx.x, kw = job / rb_count;
+        if (r >= P.m) return;
         with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
             slice_row_word<E, SID>(P.A, P.lda, P.m, P.k, P.Apl, P.Mp, P.K64p, err, r, kw);
         });
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(kThreads) void batched_slice_kernel(const BatchProd
         with_schedule<EMIN, EMAX>(P.e, P.sid, [&]<int E, int SID>() {
             uint64_t pl[E];
             load_col_planes_tile<E>(P.B, P.ldb, P.k, P.n, err, j0, kw, lane, tiles[wave], pl);
-            store_operands<E, SID, true>(pl, P.Bpl + kw * P.Np + j0 + lane, P.K64p * P.Np);
+            if (j0 + lane < P.n) store_operands<E, SID, true>(pl, P.Bpl + kw * P.Np + j0 + lane, P.K64p * P.Np);
         });
     }
 }
