@@ -592,9 +592,11 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
 }
 
 // Persistent form: workgroups take (product, planes, tile) items in order
-// from *counter; the planes of an item run as one pipeline.
+// from *counter; the planes of an item run as one pipeline.  The 128x128
+// form is held to 128 VGPRs (four waves per SIMD, no spills), which serves
+// the short items of a batch better than three.
 template <int BM, int BN, int WM, int WN, int FA, int FB>
-__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_persistent(
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(BM == 128 ? 4 : 2))) void gemm_fp4_persistent(
     const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
     int* __restrict__ counter)
 {
