@@ -1,12 +1,13 @@
 """Benchmark: dense C = A*B over F_256 (f = 0x11D), 8192 x 8192 x 8192, on one MI355X.
 
 One step is the whole product pipeline on device-resident uint8 inputs: slice
-A and B into Karatsuba operand planes, the 27 GF(2) plane products, and the
-fused recombination / reduction mod f / clinging into C.  The line printed
-also carries the roofline of the dominant kernel (the plane products, int8
-MFMA), the CPU oracle timed on a bounded sample, the batched-vs-plain speedup
-on 512 mixed products and the served p50/p99 latency (see --no-batched,
---no-serve).
+A and B into the operand planes of the field's product schedule, the 24
+GF(2) plane products (fp4 MFMA on 0/1 operands, exact counts), and the fused
+recombination / reduction mod f / clinging into C.  The line printed also
+carries the roofline of the dominant kernel (the plane products), the CPU
+oracle timed on the same product (its rows compared with the timed C), the
+batched-vs-plain speedup on 512 mixed products and the served p50/p99
+latency with every served result verified (see --no-batched, --no-serve).
 """
 from __future__ import annotations
 
@@ -64,7 +65,8 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="f256_8192")
     ap.add_argument("--kernel", type=int, default=-1, help="force a product kernel (-1 = autotuned)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU oracle sample budget")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU oracle budget (the whole 8192^3 product takes about 12 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
@@ -72,6 +74,12 @@ def parse_args():
     ap.add_argument("--no-echelon", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-budget-mib", type=int, default=1024,
+                    help="device memory for resident planes of admitted requests")
+    ap.add_argument("--serve-inflight", type=int, default=256)
+    ap.add_argument("--serve-bypass", type=int, default=16,
+                    help="admissions allowed past an oldest request waiting for memory")
+    ap.add_argument("--no-serve-verify", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: a calibration copy of --copy-mib MiB, then "
@@ -85,24 +93,41 @@ def log(args, *msg):
         print("[bench]", *msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, B, e, f, budget_s, workload_mod=None, echelon=False, no_trsm=False):
-    """The oracle on whole rows of the same product until the budget is used."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, B, C_gpu, e, f, budget_s, workload_mod=None, echelon=False, no_trsm=False):
+    """The oracle on whole rows of the same product until the budget is used
+    (all of them when it allows), each row compared with the timed GPU C."""
+    import numpy as np
     import oracle
     threads = oracle.max_threads()
+    m = A.shape[0]
     k, n = B.shape
-    rows, spent, chunk = 0, 0.0, 16
-    while spent < budget_s and rows + chunk <= A.shape[0]:
+    rows, spent, chunk, mismatched = 0, 0.0, 16, 0
+    while spent < budget_s and rows < m:
+        chunk = min(chunk, m - rows)
         t0 = time.perf_counter()
-        oracle.matmul(A[rows:rows + chunk], B, e, f, nthreads=threads)
+        part = oracle.matmul(A[rows:rows + chunk], B, e, f, nthreads=threads)
         dt = time.perf_counter() - t0
+        mismatched += int(np.count_nonzero(np.any(part != C_gpu[rows:rows + chunk], axis=1)))
         spent += dt
         rows += chunk
         if dt < budget_s / 8:
             chunk *= 2
     macs = rows * k * n
     out = {"value": macs / spent, "unit": "element-MAC/s", "cores": threads, "kind": "oracle",
-           "sample": f"{rows} of {A.shape[0]} rows of C ({rows}x{k}x{n} element-MAC), "
-                     f"{spent:.1f} s on {threads} threads"}
+           "cpu_model": cpu_model(),
+           "sample": f"{rows} of {m} rows of C ({rows}x{k}x{n} element-MAC), "
+                     f"{spent:.1f} s on {threads} threads",
+           "rows_compared_with_gpu": rows, "rows_mismatched": mismatched}
     if workload_mod is not None and not no_trsm:
         # The oracle's triangular solve (Section 4.3 row algorithm) on a
         # column sample of the TRSM leg's smallest system.
@@ -339,22 +364,20 @@ def echelon_leg(g, torch, workload, log, reps=3):
     return res
 
 
-def serve_leg(g, torch, workload, log, count=10000, budget=4 << 30, max_inflight=64, load=0.7):
+def serve_leg(g, torch, workload, log, count=10000, budget=1 << 30, max_inflight=256, bypass=16,
+              load=0.7, verify=True):
     """Served requests: n log-uniform in [64, 4096], e ~ U{2..10}.  A closed-loop
     run (all requests at t=0) gives the saturated rate; an open-loop Poisson
-    run at `load` times that rate gives the latencies."""
+    run at `load` times that rate gives the latencies.  Afterwards every
+    served result is compared, byte for byte, with the same product computed
+    alone by gf2e_mul.  Returns the result block and what the oracle's check
+    of every result needs (see serving_freivalds)."""
     import numpy as np
     specs = workload.serve_specs(count)
-    gen = workload.rng(4, 2)
-    nmax = max(n for _, _, n in specs)
-    # Inputs: one device pool per field, each request reads its leading n x n
-    # window (entries are uniform in the field; values do not change the work).
-    pools = {}
-    for e in sorted({e for e, _, _ in specs}):
-        a = workload.field_matrix(gen, nmax, nmax, e)
-        b = workload.field_matrix(gen, nmax, nmax, e)
-        pools[e] = (torch.from_numpy(a).to(g.elem_dtype(e)).cuda(),
-                    torch.from_numpy(b).to(g.elem_dtype(e)).cuda())
+    # Inputs: one pool per field, each request reads its leading n x n window.
+    pools = workload.serve_pools(specs)
+    dpools = {e: (torch.from_numpy(a).to(g.elem_dtype(e)).cuda(),
+                  torch.from_numpy(b).to(g.elem_dtype(e)).cuda()) for e, (a, b) in pools.items()}
     # Outputs: a distinct region per request.
     tot = {1: 0, 2: 0}
     for e, _, n in specs:
@@ -364,7 +387,7 @@ def serve_leg(g, torch, workload, log, count=10000, budget=4 << 30, max_inflight
     As, Bs, Cs, es, fs = [], [], [], [], []
     off = {1: 0, 2: 0}
     for e, f, n in specs:
-        A, B = pools[e]
+        A, B = dpools[e]
         As.append(A[:n, :n])
         Bs.append(B[:n, :n])
         w = 1 if e <= 8 else 2
@@ -375,36 +398,97 @@ def serve_leg(g, torch, workload, log, count=10000, budget=4 << 30, max_inflight
         fs.append(f)
     emacs = sum(n ** 3 for _, _, n in specs)
     ctx = g.Context(0)
-    srv = g.Server(ctx, memory_budget=budget, max_inflight=max_inflight)
+    srv = g.Server(ctx, memory_budget=budget, max_inflight=max_inflight, bypass_limit=bypass)
     # warm-up on a prefix (first use of every kernel)
     srv.run_trace(As[:64], Bs[:64], Cs[:64], es[:64], fs[:64], [0.0] * 64)
+    st0 = srv.stats()
     log(f"serving: closed-loop run of {count} requests")
     t0 = time.perf_counter()
     closed = srv.run_trace(As, Bs, Cs, es, fs, [0.0] * count)
     closed_s = time.perf_counter() - t0
+    st1 = srv.stats()
     sat_rate = count / closed_s
     rate = load * sat_rate
     arrivals = workload.poisson_arrivals(count, rate)
     log(f"serving: open-loop Poisson run at {rate:.0f} req/s")
+    for c in Cs:  # the open-loop run must write every result afresh
+        c.fill_(0)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     opened = srv.run_trace(As, Bs, Cs, es, fs, arrivals)
     open_s = time.perf_counter() - t0
     lat = np.array([t["t_done_ns"] for t in opened]) / 1e9 - np.asarray(arrivals)
     st = srv.stats()
     srv.close()
+
+    def delta(key, a, b):
+        return b[key] - a[key]
+
+    res = {"requests": count, "memory_budget_bytes": budget, "max_inflight": max_inflight,
+           "bypass_limit": bypass, "element_macs": emacs,
+           "saturated_req_per_s": round(sat_rate, 1),
+           "saturated_element_mac_per_s": emacs / closed_s,
+           "offered_req_per_s": round(rate, 1), "load": load,
+           "throughput_req_per_s": round(count / open_s, 1),
+           "throughput_element_mac_per_s": emacs / open_s,
+           "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+           "max_ms": round(float(lat.max()) * 1e3, 3),
+           "open_loop": {"memory_waits": delta("memory_waits", st1, st),
+                         "bypass_admissions": delta("bypass_admissions", st1, st),
+                         "iterations": delta("iterations", st1, st),
+                         "shared_iterations": delta("shared_iterations", st1, st)},
+           "closed_loop": {"memory_waits": delta("memory_waits", st0, st1),
+                           "bypass_admissions": delta("bypass_admissions", st0, st1),
+                           "iterations": delta("iterations", st0, st1),
+                           "shared_iterations": delta("shared_iterations", st0, st1)},
+           "peak_inflight": st["peak_inflight"], "max_iteration_requests": st["max_iteration_requests"],
+           "peak_arena_bytes": st["peak_arena_bytes"],
+           "status_errors": sum(1 for t in opened if t["status"] != 0)}
+    if verify:
+        # Every open-loop result against the same product computed alone
+        # (one stream, a flag per request, one synchronisation at the end).
+        log("serving: comparing every served result with the product computed alone")
+        scratch = {1: torch.empty(4096 * 4096, dtype=torch.uint8, device="cuda"),
+                   2: torch.empty(4096 * 4096, dtype=torch.int16, device="cuda")}
+        diff = torch.zeros(count, dtype=torch.int32, device="cuda")
+        for i, (e, f, n) in enumerate(specs):
+            alone = scratch[1 if e <= 8 else 2][:n * n].view(n, n)
+            ctx.mul_async(As[i], Bs[i], e, f, out=alone)
+            diff[i] = (alone != Cs[i]).any().to(torch.int32)
+        ctx.sync()
+        res["alone_vs_mix_mismatches"] = int(diff.sum().item())
     ctx.close()
-    return {"requests": count, "memory_budget_bytes": budget, "max_inflight": max_inflight,
-            "element_macs": emacs,
-            "saturated_req_per_s": round(sat_rate, 1),
-            "saturated_element_mac_per_s": emacs / closed_s,
-            "offered_req_per_s": round(rate, 1), "load": load,
-            "throughput_req_per_s": round(count / open_s, 1),
-            "throughput_element_mac_per_s": emacs / open_s,
-            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-            "max_ms": round(float(lat.max()) * 1e3, 3),
-            "peak_inflight": st["peak_inflight"], "iterations": st["iterations"],
-            "peak_arena_bytes": st["peak_arena_bytes"]}
+    state = {"specs": specs, "pools": pools, "Cs": Cs} if verify else None
+    return res, state
+
+
+def serving_freivalds(state, log):
+    """The oracle's Freivalds check over F_{2^e} on every served result, with
+    ceil(64/e) random vectors each (a wrong result passes with probability at
+    at most 2^-64), plus the oracle's whole product on a seeded sample of
+    requests.  Returns (failures, sample mismatches, seconds)."""
+    import numpy as np
+    import oracle
+    import workload
+    t0 = time.perf_counter()
+    gen = workload.rng(4, 5)
+    bad = 0
+    for i, (e, f, n) in enumerate(state["specs"]):
+        a, b = state["pools"][e]
+        R = workload.freivalds_vectors(gen, n, e)
+        bad += int(oracle.freivalds(a[:n, :n], b[:n, :n], state["Cs"][i].cpu().numpy(), e, f, R) != 0)
+        if i % 2000 == 1999:
+            log(f"serving: Freivalds checked {i + 1} results")
+    small = [i for i, (_, _, n) in enumerate(state["specs"]) if n <= 512]
+    sample = np.random.default_rng(4).choice(small, min(32, len(small)), replace=False)
+    sample_bad = 0
+    for i in sample:
+        e, f, n = state["specs"][i]
+        a, b = state["pools"][e]
+        sample_bad += int(not np.array_equal(state["Cs"][i].cpu().numpy(),
+                                             oracle.matmul(a[:n, :n], b[:n, :n], e, f)))
+    return bad, len(sample), sample_bad, time.perf_counter() - t0
 
 
 def main():
@@ -465,6 +549,7 @@ def main():
     ctx.profile(False)
     ms_per_step = elapsed * 1e3 / args.steps
     value = m * k * n / (ms_per_step / 1e3)
+    C_timed = None if args.no_cpu else C.cpu().numpy()  # the timed steps' result
 
     # GF(2) products of m x k x n per element product: t(e) for the schedule
     # form, e^2 (as one product of m x ek x en) for the alpha form.
@@ -541,13 +626,26 @@ def main():
         out["echelon"] = echelon_leg(g, torch, workload, lambda *a: log(args, *a))
     if not args.no_batched:
         out["batched"] = batched_leg(g, torch, workload, lambda *a: log(args, *a))
+    serve_state = None
     if not args.no_serve:
-        out["serving"] = serve_leg(g, torch, workload, lambda *a: log(args, *a))
+        out["serving"], serve_state = serve_leg(
+            g, torch, workload, lambda *a: log(args, *a), budget=args.serve_budget_mib << 20,
+            max_inflight=args.serve_inflight, bypass=args.serve_bypass,
+            verify=not args.no_serve_verify)
 
     if not args.no_cpu:
-        log(args, "timing the CPU oracle on a row sample")
-        out["cpu_baseline"] = cpu_baseline(A, B, e, f, args.cpu_seconds, workload,
+        log(args, "timing the CPU oracle on the benchmark product")
+        out["cpu_baseline"] = cpu_baseline(A, B, C_timed, e, f, args.cpu_seconds, workload,
                                            echelon=not args.no_echelon, no_trsm=args.no_trsm)
+        if serve_state is not None:
+            log(args, "serving: the oracle's Freivalds check on every served result")
+            bad, nsample, sample_bad, secs = serving_freivalds(serve_state, lambda *a: log(args, *a))
+            out["serving"]["freivalds_failures"] = bad
+            out["serving"]["freivalds_trials"] = "ceil(64/e) per result"
+            out["serving"]["oracle_sample"] = {"requests": nsample, "mismatched": sample_bad}
+            out["serving"]["verified"] = (bad == 0 and sample_bad == 0 and
+                                          out["serving"].get("alone_vs_mix_mismatches") == 0)
+            out["serving"]["verify_s"] = round(secs, 1)
 
     print(json.dumps(out), flush=True)
 

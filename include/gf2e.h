@@ -138,8 +138,17 @@ int gf2e_batch_info(gf2e_ctx* ctx, gf2e_batch_stats* out);
  * and runs iterations of the persistent plane-product kernel over the tiles
  * of every admitted request (at most `quantum_macs` bit-MACs per iteration),
  * so requests that arrive while others are on the GPU share its launches.
- * Results are identical to gf2e_mul of the same product.  A, B, C passed to
- * submit must stay valid and untouched until the request is waited for. */
+ * When the oldest waiting request does not fit the free memory, later
+ * requests that fit may be admitted ahead of it, at most `bypass_limit`
+ * times for each oldest request (0: strict arrival order).  Results are
+ * identical to gf2e_mul of the same product.
+ *
+ * Input readiness: submit records an event on `stream` (a hipStream_t as
+ * void*, NULL = the null stream), and the server's own stream waits for that
+ * event before it reads A and B, so the inputs may still be being written by
+ * work enqueued on `stream` before the call.  A, B, C must stay valid, and
+ * A and B unchanged, until the request is waited for; C is complete when
+ * gf2e_server_wait returns (or poll reports done). */
 typedef struct gf2e_server gf2e_server;
 
 typedef struct {
@@ -147,6 +156,7 @@ typedef struct {
     int max_inflight;                /* admitted requests at once (1..4096) */
     int64_t quantum_macs;            /* plane-product bit-MACs per iteration; 0 = no limit */
     int64_t max_items_per_iteration; /* tile items per iteration; 0 = 262144 */
+    int bypass_limit;                /* admissions past a waiting oldest request (>= 0) */
 } gf2e_server_config;
 
 typedef struct {
@@ -159,24 +169,29 @@ typedef struct {
 typedef struct {
     int64_t completed, iterations, element_macs, peak_arena_bytes;
     int peak_inflight;
+    int64_t memory_waits;      /* requests that found the memory budget full at least once */
+    int64_t bypass_admissions; /* admissions ahead of an older request waiting for memory */
+    int64_t shared_iterations; /* iterations holding tiles of two or more requests */
+    int max_iteration_requests; /* most requests with tiles in one iteration */
 } gf2e_server_counters;
 
 int gf2e_server_create(gf2e_ctx* ctx, const gf2e_server_config* cfg, gf2e_server** out);
 /* Drains every submitted request, then frees the server. */
 void gf2e_server_destroy(gf2e_server* srv);
-/* Validates and queues a request (never blocks).  GF2E_EBUSY: its footprint
- * exceeds the whole budget, so it could never be admitted. */
+/* Validates and queues a request (never blocks on the GPU).  GF2E_EBUSY: its
+ * footprint exceeds the whole budget, so it could never be admitted. */
 int gf2e_server_submit(gf2e_server* srv, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
-                       uint32_t f, uint64_t* ticket);
+                       uint32_t f, void* stream, uint64_t* ticket);
 int gf2e_server_poll(gf2e_server* srv, uint64_t ticket, int* done, gf2e_req_times* times);
 /* Blocks until the request is done; returns its status and forgets it. */
 int gf2e_server_wait(gf2e_server* srv, uint64_t ticket, gf2e_req_times* times);
 int gf2e_server_stats(gf2e_server* srv, gf2e_server_counters* out);
 /* Open-loop driver: submits request i at arrival_s[i] seconds after the call
- * starts, then waits for all; out[i] gets times relative to that start. */
+ * starts (inputs ordered after `stream` as in submit), then waits for all;
+ * out[i] gets times relative to that start. */
 int gf2e_server_run_trace(gf2e_server* srv, int count, const gf2e_mat* A, const gf2e_mat* B,
                           gf2e_mat* C, const int* e, const uint32_t* f, const double* arrival_s,
-                          gf2e_req_times* out);
+                          void* stream, gf2e_req_times* out);
 
 /* Blocking form: enqueue on the null stream, wait, report device errors. */
 int gf2e_mul(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,

@@ -285,28 +285,52 @@ int64_t gf2e_oracle_freivalds(int e, uint32_t f, int64_t m, int64_t k, int64_t n
         return ORC_ERANGE;
     }
     if (nthreads <= 0) nthreads = omp_get_max_threads();
+    /* BR = B * R, then per row i of A: (A * BR)_i and (C * R)_i.  Each sum
+     * is accumulated term by term in the order of its index l or j, the t
+     * columns side by side (XOR is commutative, so this is the same sum).
+     * Products go through the tables: a * b = exp[log a + log b], with the
+     * logarithms of R and BR looked up once. */
+    uint32_t* logR = (uint32_t*)malloc((size_t)(n * t + 1) * sizeof(uint32_t));
     uint32_t* BR = (uint32_t*)calloc((size_t)(k * t + 1), sizeof(uint32_t));
+    if (!logR || !BR) { free(logR); free(BR); free(T); return ORC_EINVAL; }
+    for (int64_t x = 0; x < n * t; ++x) logR[x] = T->log[get_el(R, wide, x)];
     int64_t diff = 0;
 #pragma omp parallel for num_threads(nthreads) schedule(static)
-    for (int64_t l = 0; l < k; ++l)
+    for (int64_t l = 0; l < k; ++l) {
+        uint32_t* br = BR + l * t;
         for (int64_t j = 0; j < n; ++j) {
-            uint32_t b = get_el(B, wide, l * ldb + j);
-            for (int64_t s = 0; s < t; ++s)
-                BR[l * t + s] ^= tab_mul(T, b, get_el(R, wide, j * t + s));
+            const uint32_t lb = T->log[get_el(B, wide, l * ldb + j)];
+            const uint32_t* lr = logR + j * t;
+            for (int64_t s = 0; s < t; ++s) br[s] ^= T->exp[lb + lr[s]];
         }
-#pragma omp parallel for num_threads(nthreads) schedule(static) reduction(+ : diff)
-    for (int64_t i = 0; i < m; ++i) {
-        int row_bad = 0;
-        for (int64_t s = 0; s < t; ++s) {
-            uint32_t lhs = 0, rhs = 0;
-            for (int64_t l = 0; l < k; ++l)
-                lhs ^= tab_mul(T, get_el(A, wide, i * lda + l), BR[l * t + s]);
-            for (int64_t j = 0; j < n; ++j)
-                rhs ^= tab_mul(T, get_el(C, wide, i * ldc + j), get_el(R, wide, j * t + s));
-            if (lhs != rhs) row_bad = 1;
-        }
-        diff += row_bad;
+        for (int64_t s = 0; s < t; ++s) br[s] = T->log[br[s]];  /* keep log(BR) */
     }
+#pragma omp parallel num_threads(nthreads) reduction(+ : diff)
+    {
+        uint32_t* acc = (uint32_t*)calloc((size_t)(2 * t + 1), sizeof(uint32_t));
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < m; ++i) {
+            uint32_t* lhs = acc;
+            uint32_t* rhs = acc + t;
+            memset(acc, 0, (size_t)(2 * t) * sizeof(uint32_t));
+            for (int64_t l = 0; l < k; ++l) {
+                const uint32_t la = T->log[get_el(A, wide, i * lda + l)];
+                const uint32_t* lbr = BR + l * t;
+                for (int64_t s = 0; s < t; ++s) lhs[s] ^= T->exp[la + lbr[s]];
+            }
+            for (int64_t j = 0; j < n; ++j) {
+                const uint32_t lc = T->log[get_el(C, wide, i * ldc + j)];
+                const uint32_t* lr = logR + j * t;
+                for (int64_t s = 0; s < t; ++s) rhs[s] ^= T->exp[lc + lr[s]];
+            }
+            int row_bad = 0;
+            for (int64_t s = 0; s < t; ++s)
+                if (lhs[s] != rhs[s]) row_bad = 1;
+            diff += row_bad;
+        }
+        free(acc);
+    }
+    free(logR);
     free(BR);
     free(T);
     return diff;

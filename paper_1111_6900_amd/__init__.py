@@ -55,7 +55,8 @@ class BatchStats(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_int64), ("max_inflight", ctypes.c_int),
-                ("quantum_macs", ctypes.c_int64), ("max_items_per_iteration", ctypes.c_int64)]
+                ("quantum_macs", ctypes.c_int64), ("max_items_per_iteration", ctypes.c_int64),
+                ("bypass_limit", ctypes.c_int)]
 
 
 class ReqTimes(ctypes.Structure):
@@ -66,7 +67,9 @@ class ReqTimes(ctypes.Structure):
 class ServerCounters(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("iterations", ctypes.c_int64),
                 ("element_macs", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_int64),
-                ("peak_inflight", ctypes.c_int)]
+                ("peak_inflight", ctypes.c_int), ("memory_waits", ctypes.c_int64),
+                ("bypass_admissions", ctypes.c_int64), ("shared_iterations", ctypes.c_int64),
+                ("max_iteration_requests", ctypes.c_int)]
 
 
 _lib = None
@@ -93,11 +96,11 @@ _SIGS = {
     "gf2e_batch_info": (_i32, [_vp, _P(BatchStats)]),
     "gf2e_server_create": (_i32, [_vp, _P(ServerConfig), _P(_vp)]),
     "gf2e_server_destroy": (None, [_vp]),
-    "gf2e_server_submit": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _P(ctypes.c_uint64)]),
+    "gf2e_server_submit": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp, _P(ctypes.c_uint64)]),
     "gf2e_server_poll": (_i32, [_vp, ctypes.c_uint64, _P(_i32), _P(ReqTimes)]),
     "gf2e_server_wait": (_i32, [_vp, ctypes.c_uint64, _P(ReqTimes)]),
     "gf2e_server_stats": (_i32, [_vp, _P(ServerCounters)]),
-    "gf2e_server_run_trace": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gf2e_server_run_trace": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_strerror": (ctypes.c_char_p, [_i32]),
     "gf2e_field_check": (_i32, [_i32, _u32]),
     "gf2e_num_products": (_i32, [_i32, _u32]),
@@ -475,9 +478,11 @@ class Server:
     """Continuous-batching request loop (see gf2e_server_* in include/gf2e.h)."""
 
     def __init__(self, ctx: Context, memory_budget: int = 4 << 30, max_inflight: int = 64,
-                 quantum_macs: int = 1 << 40, max_items_per_iteration: int = 0):
+                 quantum_macs: int = 1 << 40, max_items_per_iteration: int = 0,
+                 bypass_limit: int = 0):
         self.ctx = ctx
-        cfg = ServerConfig(memory_budget, max_inflight, quantum_macs, max_items_per_iteration)
+        cfg = ServerConfig(memory_budget, max_inflight, quantum_macs, max_items_per_iteration,
+                           bypass_limit)
         h = ctypes.c_void_p()
         _check(lib().gf2e_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)),
                "gf2e_server_create")
@@ -496,7 +501,9 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, A, B, e: int, f: int, out=None) -> int:
+    def submit(self, A, B, e: int, f: int, out=None, stream=None) -> int:
+        """Queue A*B; the server reads A and B after the work already enqueued
+        on `stream` (default: torch's current stream)."""
         _check_elem(A, e, "A")
         _check_elem(B, e, "B")
         if out is None:
@@ -504,7 +511,7 @@ class Server:
         t = ctypes.c_uint64(0)
         a, b, c = mat(A), mat(B), mat(out)
         _check(lib().gf2e_server_submit(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                                        e, f, ctypes.byref(t)), "gf2e_server_submit")
+                                        e, f, _stream_handle(stream), ctypes.byref(t)), "gf2e_server_submit")
         self._keep[t.value] = (A, B, out)  # tensors stay alive until waited for
         return t.value
 
@@ -521,7 +528,7 @@ class Server:
         _check(lib().gf2e_server_stats(self.handle, ctypes.byref(st)), "gf2e_server_stats")
         return {k: getattr(st, k) for k, _ in ServerCounters._fields_}
 
-    def run_trace(self, As, Bs, Cs, es, fs, arrival_s):
+    def run_trace(self, As, Bs, Cs, es, fs, arrival_s, stream=None):
         """Open-loop run: request i submitted at arrival_s[i] s; per-request times."""
         n = len(As)
         MA = (Mat * max(n, 1))(*[mat(t) for t in As])
@@ -531,6 +538,6 @@ class Server:
         F = (ctypes.c_uint32 * max(n, 1))(*fs)
         T = (ctypes.c_double * max(n, 1))(*[float(x) for x in arrival_s])
         out = (ReqTimes * max(n, 1))()
-        rc = lib().gf2e_server_run_trace(self.handle, n, MA, MB, MC, E, F, T, out)
+        rc = lib().gf2e_server_run_trace(self.handle, n, MA, MB, MC, E, F, T, _stream_handle(stream), out)
         _check(rc, "gf2e_server_run_trace")
         return [{k: getattr(out[i], k) for k, _ in ReqTimes._fields_} for i in range(n)]

@@ -32,8 +32,11 @@ int elem_bytes(int e) { return e <= 8 ? 1 : 2; }
 bool field_ok(int e, uint32_t f)
 {
     if (e < 2 || e > kMaxE) return false;
+    // f must have degree exactly e; this also rejects f = 0, which would
+    // otherwise match an empty cache slot below.
+    if ((f >> e) != 1u) return false;
     // The last irreducible f seen per degree (per thread): batches repeat a
-    // few fields many times.
+    // few fields many times.  A slot holds 0 until a valid f is cached.
     thread_local uint32_t known[kMaxE + 1] = {};
     if (known[e] == f) return true;
     if (!is_irreducible(e, f)) return false;

@@ -7,7 +7,10 @@
 //   1. retires requests whose completion event has fired (frees arena + slot),
 //   2. admits waiting requests in arrival order while their plane footprint
 //      fits the arena and a slot is free, slicing A and B into planes that stay
-//      resident on the device until the request completes,
+//      resident on the device until the request completes.  When the oldest
+//      waiting request does not fit, later ones that do may be admitted ahead
+//      of it, at most `bypass_limit` times per oldest request, so that a large
+//      request delays small ones only boundedly and is never starved,
 //   3. issues one iteration: up to `quantum_macs` of plane-product tiles taken
 //      from the admitted requests oldest first, as one persistent launch per
 //      tile class; a request whose last tiles are in the iteration gets its
@@ -97,6 +100,9 @@ struct Request {
     int64_t total_items = 0, next_item = 0;
     std::atomic<int> state{PENDING};
     int status = GF2E_OK;
+    int overtaken = 0;        // admissions of later requests while this one was the oldest waiting
+    bool waited_mem = false;  // found the arena full at least once
+    hipEvent_t ready_ev = nullptr;  // recorded on the submitter's stream: inputs are written
     hipEvent_t done_ev = nullptr;
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
 };
@@ -139,6 +145,8 @@ struct Server {
     std::atomic<int64_t> completed{0}, iterations{0}, element_macs{0};
     std::atomic<int64_t> arena_used{0}, peak_arena{0};
     std::atomic<int> inflight{0}, peak_inflight{0};
+    std::atomic<int64_t> memory_waits{0}, bypass_admissions{0}, shared_iterations{0};
+    std::atomic<int> max_iteration_requests{0};
 
     int64_t now_ns() const
     {
@@ -147,6 +155,7 @@ struct Server {
     void run();
     bool retire();
     bool admit();
+    void start(Request* r, int64_t off);
     bool issue_iteration();
 };
 
@@ -177,43 +186,80 @@ bool Server::retire()
     return any;
 }
 
+// Scan depth past the oldest waiting request when it does not fit.
+constexpr size_t kBypassWindow = 64;
+
 bool Server::admit()
 {
     bool any = false;
     while (!pending.empty() && !free_slots.empty() &&
            (cfg.max_inflight <= 0 || inflight < cfg.max_inflight)) {
-        Request* r = pending.front();
-        const int64_t off = arena->alloc(r->footprint);
-        if (off < 0) break;  // wait for memory: arrival order is kept
-        pending.pop_front();
-        r->arena_off = off;
-        r->slot = free_slots.back();
-        free_slots.pop_back();
-        arena_used += r->footprint;
-        peak_arena = std::max<int64_t>(peak_arena, arena_used);
-        inflight += 1;
-        peak_inflight = std::max<int>(peak_inflight, inflight);
-        uint8_t* base = arena_base + off;
-        auto a256 = [](int64_t x) { return (x + 255) / 256 * 256; };
-        r->d.Apl = reinterpret_cast<uint64_t*>(base);
-        r->d.Bpl = reinterpret_cast<uint64_t*>(base + a256(r->plan.a_bytes));
-        r->d.P = reinterpret_cast<uint64_t*>(base + a256(r->plan.a_bytes) + a256(r->plan.b_bytes));
-        h_slots[r->slot] = r->d;
-        (void)hipMemcpyAsync(d_slots + r->slot, h_slots + r->slot, sizeof(BatchProduct),
-                             hipMemcpyHostToDevice, stream);
-        int* err = d_err + r->slot;
-        if (r->d.k > 0) {
-            (void)launch_slice_rows(r->d.e, r->d.sid, r->d.A, r->d.lda, r->d.m, r->d.k, r->d.Apl, r->d.Mp,
-                                    r->d.K64p, err, stream);
-            (void)launch_slice_cols(r->d.e, r->d.sid, r->d.B, r->d.ldb, r->d.k, r->d.n, r->d.Bpl, r->d.Np,
-                                    r->d.K64p, err, stream);
+        Request* head = pending.front();
+        int64_t off = arena->alloc(head->footprint);
+        if (off >= 0) {
+            pending.pop_front();
+            start(head, off);
+            any = true;
+            continue;
         }
-        r->t_admit = now_ns();
-        r->state = ADMITTED;
-        admitted.push_back(r);
+        if (!head->waited_mem) {
+            head->waited_mem = true;
+            memory_waits += 1;
+        }
+        if (head->overtaken >= cfg.bypass_limit) break;  // arrival order from here on
+        // The oldest request waits for memory: admit the first later one that fits.
+        size_t pick = 0;
+        const size_t end = std::min(pending.size(), kBypassWindow + 1);
+        for (size_t i = 1; i < end && pick == 0; ++i) {
+            off = arena->alloc(pending[i]->footprint);
+            if (off >= 0) {
+                pick = i;
+            } else if (!pending[i]->waited_mem) {
+                pending[i]->waited_mem = true;
+                memory_waits += 1;
+            }
+        }
+        if (pick == 0) break;
+        Request* r = pending[pick];
+        pending.erase(pending.begin() + std::ptrdiff_t(pick));
+        head->overtaken += 1;
+        bypass_admissions += 1;
+        start(r, off);
         any = true;
     }
     return any;
+}
+
+// Admits r into the arena range at `off`: slot, descriptor and slicing of its
+// inputs, after the submitter's stream has written them.
+void Server::start(Request* r, int64_t off)
+{
+    r->arena_off = off;
+    r->slot = free_slots.back();
+    free_slots.pop_back();
+    arena_used += r->footprint;
+    peak_arena = std::max<int64_t>(peak_arena, arena_used);
+    inflight += 1;
+    peak_inflight = std::max<int>(peak_inflight, inflight);
+    uint8_t* base = arena_base + off;
+    auto a256 = [](int64_t x) { return (x + 255) / 256 * 256; };
+    r->d.Apl = reinterpret_cast<uint64_t*>(base);
+    r->d.Bpl = reinterpret_cast<uint64_t*>(base + a256(r->plan.a_bytes));
+    r->d.P = reinterpret_cast<uint64_t*>(base + a256(r->plan.a_bytes) + a256(r->plan.b_bytes));
+    h_slots[r->slot] = r->d;
+    (void)hipStreamWaitEvent(stream, r->ready_ev, 0);
+    (void)hipMemcpyAsync(d_slots + r->slot, h_slots + r->slot, sizeof(BatchProduct), hipMemcpyHostToDevice,
+                         stream);
+    int* err = d_err + r->slot;
+    if (r->d.k > 0) {
+        (void)launch_slice_rows(r->d.e, r->d.sid, r->d.A, r->d.lda, r->d.m, r->d.k, r->d.Apl, r->d.Mp,
+                                r->d.K64p, err, stream);
+        (void)launch_slice_cols(r->d.e, r->d.sid, r->d.B, r->d.ldb, r->d.k, r->d.n, r->d.Bpl, r->d.Np,
+                                r->d.K64p, err, stream);
+    }
+    r->t_admit = now_ns();
+    r->state = ADMITTED;
+    admitted.push_back(r);
 }
 
 bool Server::issue_iteration()
@@ -231,8 +277,10 @@ bool Server::issue_iteration()
     std::vector<Request*> finishing;
     int64_t budget = cfg.quantum_macs > 0 ? cfg.quantum_macs : INT64_MAX;
     int64_t room = max_items;
+    int contributors = 0;
     for (Request* r : admitted) {
         if (budget <= 0 || room <= 0) break;
+        if (r->next_item < r->total_items) contributors += 1;
         const GemmShape sh = gemm_shape(kClassKinds[r->cls]);
         const int64_t plane_macs = int64_t(sh.bm) * sh.bn * r->d.K64p * 64;
         while (r->next_item < r->total_items && budget > 0 && room > 0) {
@@ -279,6 +327,8 @@ bool Server::issue_iteration()
     (void)hipEventRecord(iter_ev[buf], stream);
     iter_busy[buf] = true;
     iterations += 1;
+    if (contributors >= 2) shared_iterations += 1;
+    max_iteration_requests = std::max<int>(max_iteration_requests, contributors);
     return true;
 }
 
@@ -315,7 +365,7 @@ int gf2e_server_create(gf2e_ctx* handle, const gf2e_server_config* cfg, gf2e_ser
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c || !out || !cfg || cfg->memory_budget <= 0 || cfg->max_inflight <= 0 ||
-        cfg->max_inflight > 4096)
+        cfg->max_inflight > 4096 || cfg->bypass_limit < 0)
         return GF2E_EINVAL;
     *out = nullptr;
     DeviceGuard guard(c->device);
@@ -371,6 +421,7 @@ void gf2e_server_destroy(gf2e_server* handle)
     DeviceGuard guard(s->ctx->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (auto& kv : s->all) {
+        if (kv.second->ready_ev) (void)hipEventDestroy(kv.second->ready_ev);
         if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
         delete kv.second;
     }
@@ -391,7 +442,7 @@ void gf2e_server_destroy(gf2e_server* handle)
 }
 
 int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
-                       uint32_t f, uint64_t* ticket)
+                       uint32_t f, void* stream, uint64_t* ticket)
 {
     Server* s = reinterpret_cast<Server*>(handle);
     if (!s || !ticket) return GF2E_EINVAL;
@@ -419,7 +470,13 @@ int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B
     r->total_items = (m > 0 && n > 0 && k > 0) ? ceil_div(r->plan.T, r->group) * r->tm * r->tn : 0;
     {
         DeviceGuard guard(s->ctx->device);
-        if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) return GF2E_EDEVICE;
+        if (hipEventCreateWithFlags(&r->ready_ev, hipEventDisableTiming) != hipSuccess) return GF2E_EDEVICE;
+        if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(r->ready_ev, static_cast<hipStream_t>(stream)) != hipSuccess) {
+            (void)hipEventDestroy(r->ready_ev);
+            if (r->done_ev) (void)hipEventDestroy(r->done_ev);
+            return GF2E_EDEVICE;
+        }
     }
     Request* raw = r.release();
     {
@@ -473,6 +530,7 @@ int gf2e_server_wait(gf2e_server* handle, uint64_t ticket, gf2e_req_times* times
     const int status = r->status;
     {
         DeviceGuard guard(s->ctx->device);
+        (void)hipEventDestroy(r->ready_ev);
         (void)hipEventDestroy(r->done_ev);
     }
     delete r;
@@ -488,6 +546,10 @@ int gf2e_server_stats(gf2e_server* handle, gf2e_server_counters* out)
     out->element_macs = s->element_macs;
     out->peak_arena_bytes = s->peak_arena;
     out->peak_inflight = s->peak_inflight;
+    out->memory_waits = s->memory_waits;
+    out->bypass_admissions = s->bypass_admissions;
+    out->shared_iterations = s->shared_iterations;
+    out->max_iteration_requests = s->max_iteration_requests;
     return GF2E_OK;
 }
 
@@ -496,7 +558,7 @@ int gf2e_server_stats(gf2e_server* handle, gf2e_server_counters* out)
 // are reported relative to the start of the call.
 int gf2e_server_run_trace(gf2e_server* handle, int count, const gf2e_mat* A, const gf2e_mat* B,
                           gf2e_mat* C, const int* e, const uint32_t* f, const double* arrival_s,
-                          gf2e_req_times* out)
+                          void* stream, gf2e_req_times* out)
 {
     Server* s = reinterpret_cast<Server*>(handle);
     if (!s || count < 0 || (count > 0 && (!A || !B || !C || !e || !f || !arrival_s || !out)))
@@ -507,7 +569,7 @@ int gf2e_server_run_trace(gf2e_server* handle, int count, const gf2e_mat* A, con
     int first_error = GF2E_OK;
     for (int i = 0; i < count; ++i) {
         std::this_thread::sleep_until(start + std::chrono::nanoseconds(int64_t(arrival_s[i] * 1e9)));
-        const int rc = gf2e_server_submit(handle, &A[i], &B[i], &C[i], e[i], f[i], &tickets[i]);
+        const int rc = gf2e_server_submit(handle, &A[i], &B[i], &C[i], e[i], f[i], stream, &tickets[i]);
         if (rc) {
             tickets[i] = 0;
             out[i] = {0, 0, 0, rc};

@@ -65,6 +65,40 @@ def test_field_check():
         assert not g.field_check(e, f), (e, hex(f))
 
 
+def _field_answers(pairs):
+    """field_check and num_products for each (e, f), computed on a thread
+    of their own, so that no earlier call has filled that thread's cache of
+    the last valid f per degree."""
+    import threading
+    g = _gf2e()
+    out = []
+
+    def run():
+        for e, f in pairs:
+            try:
+                n = g.num_products(e, f)
+            except g.GF2EError as err:
+                n = err.code
+            out.append((g.field_check(e, f), n))
+
+    t = threading.Thread(target=run)
+    t.start()
+    t.join()
+    return out
+
+
+def test_field_check_rejects_zero_and_wrong_degree():
+    # Section 2: f is irreducible of degree e.  f = 0 and an irreducible f
+    # of another degree are both rejected, on a fresh thread and after a
+    # valid f of the same degree has been seen.
+    bad = [(8, 0), (2, 0), (10, 0), (16, 0), (8, 0x13), (4, 0x11D), (8, 0x409)]
+    for ok, n in _field_answers(bad):
+        assert not ok and n == -2
+    res = _field_answers([(8, 0x11D), (8, 0), (4, 0x13), (4, 0x11D), (8, 0x11D)])
+    assert [r[0] for r in res] == [True, False, True, False, True]
+    assert res[1][1] == -2 and res[3][1] == -2
+
+
 def test_field_check_agrees_with_trial_division():
     from tests import fielddef
     g = _gf2e()

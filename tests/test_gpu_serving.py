@@ -46,9 +46,10 @@ def check_against_oracle(a, b, e, f, got, gen):
 
 def test_served_equals_alone_under_memory_pressure(g):
     ctx = g.Context(0)
-    # 96 MiB of plane memory and 6 slots: big requests must wait for memory
-    # while small ones keep arriving.
-    srv = g.Server(ctx, memory_budget=96 << 20, max_inflight=6, quantum_macs=1 << 36)
+    # 24 MiB of plane memory (the largest request needs 14.4 MiB, all 60
+    # together 159 MiB) and 6 slots: big requests must wait for memory while
+    # small ones keep arriving.
+    srv = g.Server(ctx, memory_budget=24 << 20, max_inflight=6, quantum_macs=1 << 36)
     gen = np.random.default_rng(2024)
     sizes = [1, 17, 64, 129, 300, 513, 700, 1024, 1500]
     reqs = []
@@ -69,8 +70,10 @@ def test_served_equals_alone_under_memory_pressure(g):
     results = [srv.wait(t) for t in tickets]
     st = srv.stats()
     assert st["completed"] == 60
-    assert 1 <= st["peak_inflight"] <= 6
-    assert st["peak_arena_bytes"] <= 96 << 20
+    assert 1 < st["peak_inflight"] <= 6
+    assert st["peak_arena_bytes"] <= 24 << 20
+    assert st["memory_waits"] >= 1          # the budget bound admission
+    assert st["shared_iterations"] >= 1     # requests shared a launch
     print("comparing with the plain path and the oracle", flush=True)
     for (e, f, a, b, A, B), (out, times) in zip(reqs, results):
         assert times["status"] == 0
@@ -107,6 +110,87 @@ def test_run_trace_poisson(g):
         e, f, n = specs[i]
         assert (host(Cs[i]) == oracle.matmul(hosts[i][0], hosts[i][1], e, f)).all(), i
     assert srv.stats()["completed"] == len(specs)
+    srv.close()
+    ctx.close()
+
+
+def _serving_inputs(g, specs, tag):
+    """Device pools per field and, per request, views of its leading n x n
+    windows and a distinct output tensor (as the benchmark lays them out)."""
+    pools = workload.serve_pools(specs, tag=tag)
+    dpools = {e: (to_dev(g, a, e), to_dev(g, b, e)) for e, (a, b) in pools.items()}
+    As, Bs, Cs = [], [], []
+    for e, f, n in specs:
+        A, B = dpools[e]
+        As.append(A[:n, :n])
+        Bs.append(B[:n, :n])
+        Cs.append(torch.empty((n, n), dtype=g.elem_dtype(e), device="cuda"))
+    return pools, As, Bs, Cs
+
+
+def test_served_workload_alone_mix_and_freivalds(g):
+    """500 requests of the served workload (e ~ U{2..10}, n log-uniform in
+    [64, 4096]) under a memory budget that binds, with bounded bypass: every
+    result equals the product computed alone, byte for byte, and passes
+    Freivalds' check over F_{2^e} with ceil(64/e) trials; a seeded sample is
+    compared with the oracle's whole product."""
+    specs = workload.serve_specs(500, lo=64, hi=4096, tag=14)
+    pools, As, Bs, Cs = _serving_inputs(g, specs, tag=14)
+    ctx = g.Context(0)
+    budget = 384 << 20
+    srv = g.Server(ctx, memory_budget=budget, max_inflight=48, bypass_limit=8)
+    arrivals = workload.poisson_arrivals(len(specs), 4000.0, tag=14)
+    print("serving 500 requests", flush=True)
+    times = srv.run_trace(As, Bs, Cs, [s[0] for s in specs], [s[1] for s in specs], arrivals)
+    st = srv.stats()
+    srv.close()
+    print(f"server counters {st}", flush=True)
+    assert all(t["status"] == 0 for t in times)
+    assert st["completed"] == len(specs)
+    assert st["peak_inflight"] > 1
+    assert st["shared_iterations"] >= 1 and st["max_iteration_requests"] >= 2
+    assert st["memory_waits"] >= 1 and st["peak_arena_bytes"] <= budget
+    print("alone vs mix", flush=True)
+    for i, (e, f, n) in enumerate(specs):
+        alone = ctx.mul(As[i], Bs[i], e, f)
+        assert torch.equal(alone, Cs[i]), (i, e, n)
+    print("Freivalds on every result", flush=True)
+    gen = workload.rng(14, 5)
+    for i, (e, f, n) in enumerate(specs):
+        a, b = pools[e]
+        R = workload.freivalds_vectors(gen, n, e)
+        assert oracle.freivalds(a[:n, :n], b[:n, :n], Cs[i].cpu().numpy(), e, f, R) == 0, (i, e, n)
+    print("oracle on a seeded sample", flush=True)
+    small = [i for i, (_, _, n) in enumerate(specs) if n <= 768]
+    for i in np.random.default_rng(14).choice(small, 12, replace=False):
+        e, f, n = specs[i]
+        a, b = pools[e]
+        assert (Cs[i].cpu().numpy() == oracle.matmul(a[:n, :n], b[:n, :n], e, f)).all(), i
+    ctx.close()
+
+
+def test_submit_waits_for_the_producer_stream(g):
+    """Inputs written on a side stream and submitted with that stream and no
+    host synchronisation: the server reads them only after the writes."""
+    e, f, n = 8, 0x11D, 512
+    gen = np.random.default_rng(77)
+    a = workload.field_matrix(gen, n, n, e)
+    b = workload.field_matrix(gen, n, n, e)
+    src_a, src_b = to_dev(g, a, e), to_dev(g, b, e)
+    A = torch.zeros_like(src_a)
+    B = torch.zeros_like(src_b)
+    torch.cuda.synchronize()
+    ctx = g.Context(0)
+    srv = g.Server(ctx, memory_budget=256 << 20, max_inflight=4)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(20_000_000)  # holds the side stream for several ms
+        A.copy_(src_a)
+        B.copy_(src_b)
+        t = srv.submit(A, B, e, f, stream=side)
+    out, tm = srv.wait(t)
+    assert tm["status"] == 0
+    assert (host(out) == oracle.matmul(a, b, e, f)).all()
     srv.close()
     ctx.close()
 

@@ -105,3 +105,14 @@ def freivalds_vectors(gen: np.random.Generator, n: int, e: int, trials=None) -> 
     wrong product passes every trial with probability at most 2^-64."""
     t = trials if trials is not None else -(-64 // e)
     return field_matrix(gen, n, t, e)
+
+
+def serve_pools(specs, tag: int = 4):
+    """Input pools of a served workload: for every field in `specs` one pair
+    (A, B) of nmax x nmax matrices, nmax the largest request size.  A request
+    of size n reads the leading n x n windows of its field's pair (entries
+    are uniform in the field either way; the values do not change the work)."""
+    gen = rng(tag, 2)
+    nmax = max(n for _, _, n in specs)
+    return {e: (field_matrix(gen, nmax, nmax, e), field_matrix(gen, nmax, nmax, e))
+            for e in sorted({e for e, _, _ in specs})}
