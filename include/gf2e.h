@@ -98,6 +98,24 @@ void gf2e_destroy(gf2e_ctx* ctx);
 int gf2e_mul_async(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
                    uint32_t f, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as gf2e_mul_async, bit for bit, computed with no hipMalloc, hipFree
+ * or event creation.  Its bit-planes live in a fixed device array of
+ * GF2E_NOALLOC_MAX_BYTES bytes, one per GPU, which the library holds until
+ * the process ends (its address is looked up by gf2e_create).  Products whose
+ * planes do not fit return GF2E_ENOMEM before anything is enqueued (for
+ * e = 8 that allows m = k = n = 2048; the plane bytes of a shape are
+ * gf2e_plane_geometry's a_bytes + b_bytes + p_bytes).  It never autotunes:
+ * it uses the context's forced or already tuned kernel, else the default.
+ * Every call on one GPU shares that array, so calls that overlap in time on
+ * one GPU (different streams, threads or contexts) race and give wrong
+ * results: order them on one stream or synchronise between them.  Entries
+ * >= 2^e are reported by gf2e_sync like gf2e_mul_async's. */
+#define GF2E_NOALLOC_MAX_BYTES ((int64_t)64 << 20)
+int gf2e_mul_noalloc_async(gf2e_ctx* ctx, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
+                           uint32_t f, void* stream);
+
 /* Many independent products C[p] = A[p] * B[p] over F_{2^e[p]} (f[p]), of
  * any shapes and fields, enqueued on `stream` as one captured HIP graph:
  * grouped slicing, one persistent grouped launch of all GF(2) plane

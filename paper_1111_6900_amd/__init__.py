@@ -84,6 +84,7 @@ _SIGS = {
     "gf2e_destroy": (None, [_vp]),
     "gf2e_mul": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
     "gf2e_mul_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
+    "gf2e_mul_noalloc_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
     "gf2e_sync": (_i32, [_vp, _vp]),
     "gf2e_mul_add_async": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32, _vp]),
     "gf2e_mul_add": (_i32, [_vp, _P(Mat), _P(Mat), _P(Mat), _i32, _u32]),
@@ -171,6 +172,8 @@ def num_products(e: int, f: int) -> int:
 
 
 MAX_PRODUCTS = 96
+# Size of the per-GPU scratch array of gf2e_mul_noalloc_async (include/gf2e.h).
+NOALLOC_MAX_BYTES = 64 << 20
 
 
 def schedule(e: int, f: int) -> dict:
@@ -289,6 +292,17 @@ class Context:
 
     def sync(self, stream=None):
         _check(lib().gf2e_sync(self.handle, _stream_handle(stream)), "gf2e_sync")
+
+    def mul_noalloc_async(self, A, B, e: int, f: int, out, stream=None):
+        """gf2e_mul_noalloc_async: C = A * B into `out` with the planes in the
+        library's fixed per-GPU scratch array (nothing allocated)."""
+        _check_elem(A, e, "A")
+        _check_elem(B, e, "B")
+        _check_elem(out, e, "out")
+        a, b, c = mat(A), mat(B), mat(out)
+        _check(lib().gf2e_mul_noalloc_async(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                            e, f, _stream_handle(stream)), "gf2e_mul_noalloc_async")
+        return out
 
     def mul(self, A, B, e: int, f: int, out=None, stream=None):
         out = self.mul_async(A, B, e, f, out=out, stream=stream)

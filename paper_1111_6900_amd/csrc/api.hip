@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,42 @@ DeviceGuard::~DeviceGuard()
 }
 
 int elem_bytes(int e) { return e <= 8 ? 1 : 2; }
+
+// Plane workspace of gf2e_mul_noalloc_async: a fixed array in device memory,
+// one per GPU, held until the process ends and shared by every call on that
+// GPU.  Host code never passes `scratch` itself to a kernel (on the host it
+// names a stand-in, not the device array); it uses the address that
+// hipGetSymbolAddress reports for the current device, kept per device.
+static __device__ __align__(256) uint64_t scratch[GF2E_NOALLOC_MAX_BYTES / 8];
+
+namespace {
+std::mutex scratch_mu;
+std::vector<void*> scratch_addr;  // per device; nullptr until looked up
+}  // namespace
+
+// Looks up the device address of `scratch` on `dev` (which must be current)
+// once; later calls return the kept address.  nullptr if the lookup failed.
+static void* scratch_on(int dev)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (dev < 0) return nullptr;
+    if (size_t(dev) >= scratch_addr.size()) scratch_addr.resize(size_t(dev) + 1, nullptr);
+    if (!scratch_addr[size_t(dev)]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_addr[size_t(dev)] = ptr;
+    }
+    return scratch_addr[size_t(dev)];
+}
+
+static void* scratch_known(int dev)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return dev >= 0 && size_t(dev) < scratch_addr.size() ? scratch_addr[size_t(dev)] : nullptr;
+}
 
 bool field_ok(int e, uint32_t f)
 {
@@ -188,9 +225,9 @@ int Ctx::ensure_workspace(int64_t bytes, hipStream_t s)
     return GF2E_OK;
 }
 
-StageTimer::StageTimer(Ctx* c, int stage, hipStream_t s) : ctx_(c), stage_(stage), s_(s)
+StageTimer::StageTimer(Ctx* c, int stage, hipStream_t s, bool on) : ctx_(c), stage_(stage), s_(s)
 {
-    if (!ctx_->prof) return;
+    if (!on || !ctx_->prof) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     (void)hipStreamIsCapturing(s, &cs);
     if (cs != hipStreamCaptureStatusNone) return;
@@ -297,31 +334,34 @@ void Ctx::save_tune_entry(uint64_t key, int choice)
 }
 
 int Ctx::exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                   int64_t ldc, hipStream_t s, bool acc)
+                   int64_t ldc, hipStream_t s, bool acc, void* planes)
 {
-    uint64_t* Apl = static_cast<uint64_t*>(ws);
+    uint64_t* Apl = static_cast<uint64_t*>(planes ? planes : ws);
     uint64_t* Bpl = Apl + p.a_bytes / 8;
     uint64_t* P = Bpl + p.b_bytes / 8;
+    // No stage timers on caller-provided planes (the path that must not
+    // create events or allocate).
+    const bool timed = planes == nullptr;
     hipError_t err;
     {
-        StageTimer t(this, GF2E_STAGE_SLICE_A, s);
+        StageTimer t(this, GF2E_STAGE_SLICE_A, s, timed);
         err = launch_slice_rows(p.e, p.sid, A, lda, p.m, p.k, Apl, p.Mp, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
-        StageTimer t(this, GF2E_STAGE_SLICE_B, s);
+        StageTimer t(this, GF2E_STAGE_SLICE_B, s, timed);
         err = p.form == kFormAlpha
                   ? launch_slice_cols_alpha(p.e, p.f, B, ldb, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s)
                   : launch_slice_cols(p.e, p.sid, B, ldb, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
-        StageTimer t(this, GF2E_STAGE_PRODUCTS, s);
+        StageTimer t(this, GF2E_STAGE_PRODUCTS, s, timed);
         err = launch_gemm(kind, p.gT, Apl, Bpl, P, p.m, p.gn, p.Mp, p.gNp, p.gK64p, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
     {
-        StageTimer t(this, GF2E_STAGE_COMBINE, s);
+        StageTimer t(this, GF2E_STAGE_COMBINE, s, timed);
         // Alpha form: result plane c is the column block c of the one product.
         err = p.form == kFormAlpha
                   ? launch_combine(p.e, p.sid, p.f, P, p.Np / 64, p.gNp / 64, p.m, p.n, C, ldc, s, acc)
@@ -562,6 +602,14 @@ int gf2e_create(gf2e_ctx** out, int device, const gf2e_config* cfg)
         return GF2E_EDEVICE;
     }
     c->load_tune_cache();
+    // The no-allocation entry point's scratch array: its address on this
+    // device, looked up once per device with the device current.
+    if (!scratch_on(device)) {
+        (void)hipFree(c->d_err);
+        (void)hipEventDestroy(c->ws_done);
+        delete c;
+        return GF2E_EDEVICE;
+    }
     *out = reinterpret_cast<gf2e_ctx*>(c);
     return GF2E_OK;
 }
@@ -608,6 +656,32 @@ int gf2e_mul_async(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_
     rc = c->mul(e, f, A, B, C, s);
     c->mark_used(s);
     return rc;
+}
+
+int gf2e_mul_noalloc_async(gf2e_ctx* handle, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, int e,
+                           uint32_t f, void* stream)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c) return GF2E_EINVAL;
+    int rc = validate_mul(A, B, C, e, f);
+    if (rc) return rc;
+    const int64_t m = A->rows, k = A->cols, n = B->cols;
+    if (m == 0 || n == 0) return GF2E_OK;
+    void* planes = scratch_known(c->device);
+    if (!planes) return GF2E_EDEVICE;
+    DeviceGuard guard(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (k == 0)
+        return launch_zero(C->data, m, n, C->ld, elem_bytes(e), s) == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+    // Form and kernel: forced, or tuned earlier, or the planner's default;
+    // this entry point never tunes (tuning allocates its inputs).
+    Plan p = make_plan(e, f, m, k, n, c->choose_form(e, f, m, k, n), true);
+    if (p.a_bytes + p.b_bytes + p.p_bytes > GF2E_NOALLOC_MAX_BYTES) {
+        p = make_plan(e, f, m, k, n, kFormSchedule, true);
+        if (p.a_bytes + p.b_bytes + p.p_bytes > GF2E_NOALLOC_MAX_BYTES) return GF2E_ENOMEM;
+    }
+    const int kind = supported_kind(c->choose_kind(p), p);
+    return c->exec_plan(p, kind, A->data, A->ld, B->data, B->ld, C->data, C->ld, s, false, planes);
 }
 
 int gf2e_sync(gf2e_ctx* handle, void* stream)

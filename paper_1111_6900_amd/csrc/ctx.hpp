@@ -114,9 +114,10 @@ struct Ctx {
     // C, all in stream order (the library's own callers use that).
     int mul(int e, uint32_t f, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C, hipStream_t s,
             bool acc = false);
-    // Launches the stages of plan p with product kernel kind; planes in ws.
+    // Launches the stages of plan p with product kernel kind; planes in
+    // `planes` (a_bytes + b_bytes + p_bytes of device memory), else in ws.
     int exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const void* B, int64_t ldb,
-                  void* C, int64_t ldc, hipStream_t s, bool acc = false);
+                  void* C, int64_t ldc, hipStream_t s, bool acc = false, void* planes = nullptr);
 
     // Buffers of the triangular solver (inverted diagonal blocks) and of
     // the echelon driver, kept apart from the product workspace.
@@ -144,7 +145,7 @@ struct Ctx {
 // Brackets one stage launch with HIP events when the context's timers are on.
 class StageTimer {
 public:
-    StageTimer(Ctx* c, int stage, hipStream_t s);
+    StageTimer(Ctx* c, int stage, hipStream_t s, bool on = true);
     ~StageTimer();
 
 private:
