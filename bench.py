@@ -42,10 +42,11 @@ def kernel_roofline(name):
     raise KeyError(name)
 
 
-def measured_traffic(workload_name, kernel_name, planes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None if there is none, the kernel source changed since, or the
-    launch then covered a different number of plane products."""
+def measured_counters(workload_name, kernel_name, planes):
+    """The committed rocprofv3 figures for this product kernel (HBM bytes per
+    launch, MFMA busy fraction, traced mean over the timed steps), or None if
+    there are none, the kernel source changed since, or the launch then
+    covered a different number of plane products."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -55,7 +56,7 @@ def measured_traffic(workload_name, kernel_name, planes):
         return None
     if hashlib.sha256(src).hexdigest() != entry["source_sha256"] or entry.get("planes") != planes:
         return None
-    return entry["traffic_bytes"]
+    return entry
 
 
 def parse_args():
@@ -565,12 +566,20 @@ def main():
     else:
         plane_bytes = 8 * (e * kwa * m + e * e * kwa * n + e * m * nwa)
     achieved = ops / (prod_ms / 1e3) / 1e12
+    prof = measured_counters(args.workload, kname, T if form == g.FORM_SCHEDULE else 1)
     roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(args.workload, kname, T if form == g.FORM_SCHEDULE else 1),
+                "traffic": prof["traffic_bytes"] if prof else None,
                 "kernel": kname, "form": ["schedule", "alpha"][form], "avg_launch_ms": round(prod_ms, 4),
+                "timer": "HIP events around every product launch on its own stream, mean over the "
+                         f"{args.steps} timed steps",
                 "algorithmic_ops_per_launch": ops,
                 "algorithmic_bytes_per_launch": plane_bytes}
+    if prof and "mfma_busy" in prof:
+        # From the committed profile of the same kernel source: rocprofv3's
+        # mean over the timed steps, and the matrix cores' busy share.
+        roofline["profile"] = {k: prof[k] for k in ("trace_timed_mean_ms", "mfma_busy", "clock_ghz", "summary")
+                               if k in prof}
     # HBM-bound stages: algorithmic bytes (elements in/out + planes written/read).
     esz = 1 if e <= 8 else 2
     kw = -(-k // 64)
