@@ -67,6 +67,7 @@ def _load():
     lib.gf2e_oracle_max_threads.restype = i32
     lib.gf2e_oracle_trsm.argtypes = [i32, u32, i32, i32, i64, i64, vp, i64, vp, i64, i32]
     lib.gf2e_oracle_echelon.argtypes = [i32, u32, i32, i64, i64, vp, i64, vp, vp]
+    lib.gf2e_oracle_ple.argtypes = [i32, u32, i64, i64, vp, i64, vp, i64, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -208,6 +209,25 @@ def echelon(A, e: int, f: int, full: bool = True):
                                        _ptr(piv)))
     r = int(rank.value)
     return E, r, piv[:r].copy()
+
+
+def ple(A, e: int, f: int):
+    """(P, L, E, Q, rank) with A[P[i]] = sum_t L[i][t] E[t] (A = P L E), by the
+    elimination loop of Section 4.1 modified as Section 4.2 describes: L is
+    m x min(m, n) lower trapezoidal with the pivots on its diagonal, E is in
+    row echelon form with leading 1 in column Q[t] of row t < rank (rows from
+    rank on are zero).  A is not modified."""
+    E = _as_field_matrix(A, e).copy()
+    m, n = E.shape
+    mn = min(m, n)
+    L = np.zeros((m, max(mn, 1)), dtype=elem_dtype(e))
+    P = np.zeros(max(m, 1), dtype=np.int64)
+    Q = np.zeros(max(mn, 1), dtype=np.int64)
+    rank = ctypes.c_int64(0)
+    _check(_load().gf2e_oracle_ple(e, f, m, n, _ptr(E), n, _ptr(L), L.shape[1], _ptr(P), _ptr(Q),
+                                   ctypes.byref(rank)))
+    r = int(rank.value)
+    return P[:m].copy(), L[:, :mn].copy(), E, Q[:r].copy(), r
 
 
 def max_threads() -> int:

@@ -455,3 +455,77 @@ int gf2e_oracle_echelon(int e, uint32_t f, int full, int64_t m, int64_t n, void*
     free(T);
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* PLE decomposition (Section 4.2).                                        */
+/* ---------------------------------------------------------------------- */
+
+/* A = P * L * E for an m x n matrix A, by the elimination loop of Section
+ * 4.1 modified as Section 4.2 describes: for each column j in turn, the
+ * first row i >= r with a nonzero entry d there is swapped into row r (its
+ * stored multipliers in L and its record in P move with it), d is recorded
+ * as L[r][r] and the row is scaled to leading entry 1 (the paper's variant:
+ * L is not unit, E has unit pivots); for every row k below, x = A[k][j] is
+ * recorded as L[k][r] and x times row r is added to row k (no row above is
+ * touched, so E is not reduced).  Columns are recorded in Q.
+ * On return: A holds E (rows 0..rank-1 in row echelon form with leading 1
+ * in column Q[t], rows rank..m-1 zero); L (m x min(m, n), row pitch ldl)
+ * holds L[i][t] for t < rank (zero for t > i and in columns rank..);
+ * P[i] is the index in the input of the row that row i of L*E equals.
+ * ORC_ERANGE if an entry is not below 2^e (nothing changed). */
+int gf2e_oracle_ple(int e, uint32_t f, int64_t m, int64_t n, void* A, int64_t lda, void* L, int64_t ldl,
+                    int64_t* P, int64_t* Q, int64_t* rank)
+{
+    if (m < 0 || n < 0 || !rank || (m > 0 && !P)) return ORC_EINVAL;
+    field_tables* T = (field_tables*)malloc(sizeof *T);
+    if (!T) return ORC_EINVAL;
+    int rc = build_tables(e, f, T);
+    if (rc != ORC_OK) { free(T); return rc; }
+    const int wide = e > 8;
+    if (!all_in_field(A, wide, m, n, lda, 1u << e)) { free(T); return ORC_ERANGE; }
+    const int64_t mn = m < n ? m : n;
+    for (int64_t i = 0; i < m; ++i) {
+        P[i] = i;
+        for (int64_t t = 0; t < mn; ++t) put_el(L, wide, i * ldl + t, 0);
+    }
+    int64_t r = 0;
+    for (int64_t j = 0; j < n && r < m; ++j) {
+        int64_t i = r;
+        while (i < m && get_el(A, wide, i * lda + j) == 0) ++i;
+        if (i == m) continue;
+        /* swap rows i and r of A, of the multipliers found so far, and of P */
+        if (i != r) {
+            for (int64_t c = 0; c < n; ++c) {
+                const uint32_t a = get_el(A, wide, i * lda + c), b = get_el(A, wide, r * lda + c);
+                put_el(A, wide, i * lda + c, b);
+                put_el(A, wide, r * lda + c, a);
+            }
+            for (int64_t t = 0; t < r; ++t) {
+                const uint32_t a = get_el(L, wide, i * ldl + t), b = get_el(L, wide, r * ldl + t);
+                put_el(L, wide, i * ldl + t, b);
+                put_el(L, wide, r * ldl + t, a);
+            }
+            const int64_t p = P[i];
+            P[i] = P[r];
+            P[r] = p;
+        }
+        /* the pivot goes to L, the row is scaled to leading entry 1 */
+        const uint32_t d = get_el(A, wide, r * lda + j);
+        put_el(L, wide, r * ldl + r, d);
+        const uint32_t dinv = T->exp[T->q - T->log[d]];
+        for (int64_t c = j; c < n; ++c) put_el(A, wide, r * lda + c, tab_mul(T, dinv, get_el(A, wide, r * lda + c)));
+        /* rows below: record the multiplier, subtract (add) its multiple */
+        for (int64_t k = r + 1; k < m; ++k) {
+            const uint32_t x = get_el(A, wide, k * lda + j);
+            if (!x) continue;
+            put_el(L, wide, k * ldl + r, x);
+            for (int64_t c = j; c < n; ++c)
+                put_el(A, wide, k * lda + c, get_el(A, wide, k * lda + c) ^ tab_mul(T, x, get_el(A, wide, r * lda + c)));
+        }
+        if (Q) Q[r] = j;
+        ++r;
+    }
+    *rank = r;
+    free(T);
+    return ORC_OK;
+}
