@@ -253,6 +253,26 @@ int gf2e_trsm(gf2e_ctx* ctx, int lower, int unit, const gf2e_mat* T, gf2e_mat* B
 int gf2e_echelonize(gf2e_ctx* ctx, gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank,
                     int64_t* pivots);
 
+/* PLE decomposition (Section 4.2, Definition PLE, in the paper's variant
+ * whose L is not unit and whose E has leading ones): A = P * L * E.
+ *   A (m x n): in place; on return rows 0..rank-1 hold E in row echelon form
+ *     (row t has its leading 1 in column Q[t], zeros below it; entries above
+ *     the pivots are not cleared) and rows rank..m-1 are zero.
+ *   L (m x min(m, n), device, caller-owned, must not overlap A): on return
+ *     L[i][t] for t < rank, lower trapezoidal (zero for t > i) with the
+ *     pivots on its diagonal, and zero in columns rank..min(m, n)-1.
+ *   P (host, m entries): row i of L * E equals row P[i] of the input A.
+ *   Q (host, min(m, n) entries, may be NULL): pivot column of row t < rank;
+ *     the pivot columns are the column rank profile of A, unique.
+ * P and L depend on which rows the pivot search picks (several valid
+ * decompositions exist); E's row space, the rank and Q do not.  Blocking
+ * (the null stream).  GF2E_ERANGE if an entry of A is >= 2^e (A and L are
+ * then unchanged), GF2E_ESHAPE if L's shape differs, GF2E_EALIAS if L
+ * overlaps A.  Computed panel by panel like gf2e_echelonize, with each
+ * panel's pivot block factored as Lk Uk on the device. */
+int gf2e_ple(gf2e_ctx* ctx, gf2e_mat* A, gf2e_mat* L, int e, uint32_t f, int64_t* rank, int64_t* P,
+             int64_t* Q);
+
 const char* gf2e_strerror(int code);
 
 /* ---- Field and schedule queries (host only; need no GPU) ---------------- */

@@ -91,6 +91,7 @@ _SIGS = {
     "gf2e_trsm_async": (_i32, [_vp, _i32, _i32, _P(Mat), _P(Mat), _i32, _u32, _vp]),
     "gf2e_trsm": (_i32, [_vp, _i32, _i32, _P(Mat), _P(Mat), _i32, _u32]),
     "gf2e_echelonize": (_i32, [_vp, _P(Mat), _i32, _u32, _i32, _P(_i64), _vp]),
+    "gf2e_ple": (_i32, [_vp, _P(Mat), _P(Mat), _i32, _u32, _P(_i64), _vp, _vp]),
     "gf2e_mul_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_set_batch_threshold": (_i32, [_vp, _i64]),
     "gf2e_tune_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -351,6 +352,23 @@ class Context:
                                      ctypes.cast(piv, ctypes.c_void_p)), "gf2e_echelonize")
         r = int(rank.value)
         return r, [int(piv[t]) for t in range(r)]
+
+    def ple(self, A, e: int, f: int, L=None):
+        """PLE decomposition in place (gf2e_ple): A becomes E; returns
+        (L, P as a list, Q as a list, rank) with input row P[i] = (L E)[i]."""
+        _check_elem(A, e, "A")
+        m, n = A.size(0), A.size(1)
+        if L is None:
+            L = torch.empty((m, min(m, n)), dtype=A.dtype, device=A.device)
+        _check_elem(L, e, "L")
+        a, l = mat(A), mat(L)
+        rank = ctypes.c_int64(0)
+        P = (ctypes.c_int64 * max(1, m))()
+        Q = (ctypes.c_int64 * max(1, min(m, n)))()
+        _check(lib().gf2e_ple(self.handle, ctypes.byref(a), ctypes.byref(l), e, f, ctypes.byref(rank),
+                              ctypes.cast(P, ctypes.c_void_p), ctypes.cast(Q, ctypes.c_void_p)), "gf2e_ple")
+        r = int(rank.value)
+        return L, [int(P[i]) for i in range(m)], [int(Q[t]) for t in range(r)], r
 
     # -- batched -------------------------------------------------------------
     def _batch_args(self, As, Bs, Cs, es, fs):

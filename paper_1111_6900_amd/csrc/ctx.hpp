@@ -137,8 +137,15 @@ struct Ctx {
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
     void* ensure_pinned(size_t bytes);
-    // Row echelon form in place (reduced when full); host-synchronous.
-    int echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s);
+    // Row echelon form in place (reduced when full); host-synchronous.  With
+    // ple (full = 0) it also returns the PLE decomposition's L (m x min(m, n),
+    // device) and P (m row indices, host).
+    struct PleOut {
+        gf2e_mat* L;
+        int64_t* P;
+    };
+    int echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s,
+                PleOut* ple = nullptr);
     void release_batches();
 };
 

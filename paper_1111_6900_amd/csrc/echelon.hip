@@ -271,6 +271,85 @@ __global__ void gather_pivot_columns_kernel(const uint16_t* orig, int64_t r, int
     st_el(G, wide, idx, orig[src * kPanel + st->cols[t]]);
 }
 
+// PLE form of a panel (Section 4.2): K = the original entries of the pivot
+// rows at the pivot columns (rp x rp, pivot order), factored K = Lk Uk
+// without row exchanges: the pivot search found row t's pivot in column t
+// after eliminating the earlier pivots, so every step has a nonzero pivot.
+// Lk is lower triangular with the pivots on its diagonal, Uk unit upper
+// triangular.  Writes Lk, Lk^{-1} and Uk^{-1} (rp x rp, pitch rp): the
+// panel's rows of E are Lk^{-1} times the pivot rows, and a row below with
+// pivot-column entries g gets the multipliers g Uk^{-1} in L.  One
+// workgroup; each step updates its whole trailing block in parallel.
+template <bool LDS_TABS>
+__global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, int64_t r, const PanelState* st,
+                                                        DevField F, int wide, void* Lk, void* Linv, void* Uinv)
+{
+    constexpr int NT = 1024, P1 = kPanel + 1;
+    __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
+    __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
+    __shared__ uint16_t K[kPanel * P1];
+    __shared__ uint16_t X[kPanel * P1];
+    const int tid = threadIdx.x, q = int(F.q), rp = st->rp;
+    if constexpr (LDS_TABS) {
+        for (int k = tid; k <= 4 * q; k += NT) sexp[k] = F.exp[k];
+        for (int k = tid; k <= q; k += NT) slog[k] = F.log[k];
+    }
+    const uint16_t* ex = LDS_TABS ? sexp : F.exp;
+    const uint32_t* lg = LDS_TABS ? slog : F.log;
+    auto mul = [&](uint32_t a, uint32_t b) { return uint32_t(ex[lg[a] + lg[b]]); };
+    for (int idx = tid; idx < rp * rp; idx += NT) {
+        const int t = idx / rp, c = idx % rp;
+        K[t * P1 + c] = orig[(r + st->rows[t]) * kPanel + st->cols[c]];
+    }
+    __syncthreads();
+    // Lk in K's lower triangle (diagonal included), Uk in its strict upper one
+    for (int t = 0; t < rp; ++t) {
+        const uint32_t inv = ex[q - int(lg[K[t * P1 + t]])];
+        for (int c = t + 1 + tid; c < rp; c += NT) K[t * P1 + c] = uint16_t(mul(K[t * P1 + c], inv));
+        __syncthreads();
+        const int w = rp - t - 1;
+        for (int idx = tid; idx < w * w; idx += NT) {
+            const int i = t + 1 + idx / w, c = t + 1 + idx % w;
+            K[i * P1 + c] ^= uint16_t(mul(K[i * P1 + t], K[t * P1 + c]));
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < rp * rp; idx += NT) {
+        const int t = idx / rp, c = idx % rp;
+        st_el(Lk, wide, idx, c <= t ? K[t * P1 + c] : 0u);
+        X[t * P1 + c] = t == c ? 1 : 0;
+    }
+    __syncthreads();
+    // Lk^{-1}: row t of X scaled by 1 / Lk[t][t], then removed from the rows below
+    for (int t = 0; t < rp; ++t) {
+        const uint32_t inv = ex[q - int(lg[K[t * P1 + t]])];
+        for (int c = tid; c <= t; c += NT) X[t * P1 + c] = uint16_t(mul(X[t * P1 + c], inv));
+        __syncthreads();
+        const int below = rp - t - 1;
+        for (int idx = tid; idx < below * (t + 1); idx += NT) {
+            const int i = t + 1 + idx / (t + 1), c = idx % (t + 1);
+            X[i * P1 + c] ^= uint16_t(mul(K[i * P1 + t], X[t * P1 + c]));
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < rp * rp; idx += NT) {
+        const int t = idx / rp, c = idx % rp;
+        st_el(Linv, wide, idx, X[t * P1 + c]);
+        X[t * P1 + c] = t == c ? 1 : 0;
+    }
+    __syncthreads();
+    // Uk^{-1} (unit diagonal): row t of X removed from the rows above, last row first
+    for (int t = rp - 1; t >= 0; --t) {
+        const int cols = rp - t;
+        for (int idx = tid; idx < t * cols; idx += NT) {
+            const int i = idx / cols, c = t + idx % cols;
+            X[i * P1 + c] ^= uint16_t(mul(K[i * P1 + t], X[t * P1 + c]));
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < rp * rp; idx += NT) st_el(Uinv, wide, idx, X[(idx / rp) * P1 + idx % rp]);
+}
+
 // Row moves of one panel on columns c0..c0+cols-1: position r + moves[j]
 // takes old row r + perm[moves[j]].  Gathered into tmp (pitch cols) first,
 // then scattered, since the moves permute the rows among themselves.
@@ -352,7 +431,8 @@ void* Ctx::ensure_pinned(size_t bytes)
     return pinned;
 }
 
-int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s)
+int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s,
+                 PleOut* ple)
 {
     const int64_t m = A->rows, n = A->cols;
     *rank = 0;
@@ -384,8 +464,8 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     const int64_t b_orig = al(m * kPanel * 2), b_cand = al(ceil_div(m, kSelRows) * kPanel * 4),
                   b_state = al(sizeof(PanelState)), b_perm = al((m + 2 * kPanel) * 4),
                   b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz),
-                  b_mv = al(2 * kPanel * n * esz);
-    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv, s);
+                  b_mv = al(2 * kPanel * n * esz), b_lu = ple ? 3 * b_w : 0;
+    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv + b_lu, s);
     if (rc) return rc;
     uint8_t* base = static_cast<uint8_t*>(aux);
     uint16_t* orig = reinterpret_cast<uint16_t*>(base);
@@ -395,6 +475,17 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     uint8_t* W = base + b_orig + 2 * b_cand + b_state + b_perm;
     uint8_t* G = W + b_w;
     uint8_t* mvbuf = G + b_g;
+    // PLE: the panel's Lk, Lk^{-1} and Uk^{-1} (panel_lu_kernel)
+    uint8_t* Lk = mvbuf + b_mv;
+    uint8_t* Lkinv = Lk + b_w;
+    uint8_t* Ukinv = Lkinv + b_w;
+    std::vector<int64_t> rowid, moved;  // PLE: input index of each current row
+    if (ple) {
+        rowid.resize(size_t(m));
+        for (int64_t i = 0; i < m; ++i) rowid[size_t(i)] = i;
+        const int64_t mn = std::min(m, n);
+        if (launch_zero(ple->L->data, m, mn, ple->L->ld, esz, s) != hipSuccess) return GF2E_EDEVICE;
+    }
 
     // The final pivot-search level writes the panel state to device memory
     // (read by later kernels) and to this mapped host copy (read by the host
@@ -505,9 +596,54 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                                perm + plen, nm, nc, wide, mvbuf);
             hipLaunchKernelGGL(scatter_rows_kernel, rows_grid(nm, nc), dim3(256), 0, s, A->data, lda, r, c0,
                                perm + plen, nm, nc, wide, mvbuf);
+            if (ple) {
+                // the moved rows take their multipliers of the earlier panels
+                // (columns 0..r-1 of L) and their input indices along
+                if (r > 0) {
+                    hipLaunchKernelGGL(gather_rows_kernel, rows_grid(nm, r), dim3(256), 0, s, ple->L->data,
+                                       ple->L->ld, r, int64_t(0), perm, perm + plen, nm, r, wide, mvbuf);
+                    hipLaunchKernelGGL(scatter_rows_kernel, rows_grid(nm, r), dim3(256), 0, s, ple->L->data,
+                                       ple->L->ld, r, int64_t(0), perm + plen, nm, r, wide, mvbuf);
+                }
+                moved.resize(size_t(nm));
+                for (int j = 0; j < nm; ++j) moved[size_t(j)] = rowid[size_t(r + hperm[moves[j]])];
+                for (int j = 0; j < nm; ++j) rowid[size_t(r + moves[j])] = moved[size_t(j)];
+            }
         }
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
 
+        if (ple) {
+            // PLE (Section 4.2): E's rows of this panel are Lk^{-1} times the
+            // pivot rows (row echelon form, leading ones), the rows below get
+            // the multipliers G Uk^{-1} in L and lose their multiples of E's
+            // rows; the rows above keep their entries (E is not reduced).
+            if (lds_tabs)
+                hipLaunchKernelGGL(panel_lu_kernel<true>, dim3(1), dim3(1024), 0, s, orig, r, st, F, wide,
+                                   static_cast<void*>(Lk), static_cast<void*>(Lkinv), static_cast<void*>(Ukinv));
+            else
+                hipLaunchKernelGGL(panel_lu_kernel<false>, dim3(1), dim3(1024), 0, s, orig, r, st, F, wide,
+                                   static_cast<void*>(Lk), static_cast<void*>(Lkinv), static_cast<void*>(Ukinv));
+            if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
+            const gf2e_mat Li{Lkinv, rp, rp, rp};
+            gf2e_mat Ep{Ad + (r * lda + c0) * esz, rp, nc, lda};
+            if ((rc = mul(e, f, &Li, &Ep, &Ep, s))) return rc;
+            uint8_t* Ld = static_cast<uint8_t*>(ple->L->data);
+            const int64_t ldl = ple->L->ld;
+            if (hipMemcpy2DAsync(Ld + (r * ldl + r) * esz, size_t(ldl * esz), Lk, size_t(rp * esz),
+                                 size_t(rp * esz), size_t(rp), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return GF2E_EDEVICE;
+            const int64_t below = m - r - rp;
+            if (below > 0) {
+                const gf2e_mat Gb{G + (r + rp) * rp * esz, below, rp, rp};
+                const gf2e_mat Ui{Ukinv, rp, rp, rp};
+                gf2e_mat Lb{Ld + ((r + rp) * ldl + r) * esz, below, rp, ldl};
+                if ((rc = mul(e, f, &Gb, &Ui, &Lb, s))) return rc;
+                gf2e_mat Cb{Ad + ((r + rp) * lda + c0) * esz, below, nc, lda};
+                if ((rc = mul(e, f, &Lb, &Ep, &Cb, s, true))) return rc;
+            }
+            r += rp;
+            continue;
+        }
         // X1 = W * (pivot rows), in place over the pivot rows; then every
         // other row (from r on, or all rows for the reduced form) += G * X1,
         // where G is zero on the pivot rows, so that they keep X1.  Both
@@ -524,6 +660,8 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         r += rp;
     }
     *rank = r;
+    if (ple)
+        for (int64_t i = 0; i < m; ++i) ple->P[i] = rowid[size_t(i)];
     return GF2E_OK;
 }
 
@@ -544,6 +682,34 @@ int gf2e_echelonize(gf2e_ctx* handle, gf2e_mat* A, int e, uint32_t f, int full, 
     hipStream_t s = nullptr;
     c->order_stream(s);
     rc = c->echelon(A, e, f, full != 0, rank, pivots, s);
+    c->mark_used(s);
+    if (rc) return rc;
+    return gf2e_sync(handle, nullptr);
+}
+
+int gf2e_ple(gf2e_ctx* handle, gf2e_mat* A, gf2e_mat* L, int e, uint32_t f, int64_t* rank, int64_t* P,
+             int64_t* Q)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c || !rank || !L) return GF2E_EINVAL;
+    int rc = check_mat(A);
+    if (rc || (rc = check_mat(L))) return rc;
+    if (!field_ok(e, f)) return GF2E_EFIELD;
+    const int64_t m = A->rows, n = A->cols;
+    if (L->rows != m || L->cols != std::min(m, n)) return GF2E_ESHAPE;
+    if (m > 0 && !P) return GF2E_EINVAL;
+    if (overlaps(A, L, elem_bytes(e))) return GF2E_EALIAS;
+    *rank = 0;
+    if (m == 0) return GF2E_OK;
+    if (n == 0) {
+        for (int64_t i = 0; i < m; ++i) P[i] = i;
+        return GF2E_OK;
+    }
+    DeviceGuard guard(c->device);
+    hipStream_t s = nullptr;
+    c->order_stream(s);
+    Ctx::PleOut out{L, P};
+    rc = c->echelon(A, e, f, 0, rank, Q, s, &out);
     c->mark_used(s);
     if (rc) return rc;
     return gf2e_sync(handle, nullptr);
