@@ -358,9 +358,19 @@ def echelon_leg(g, torch, workload, log, reps=3):
         ms = float(np.median(times))
         row = {"m": m, "n": m, "e": e, "rank": r, "ms": round(ms, 2),
                "element_mac_per_s": m * m * r / (ms / 1e3)}
+        # The PLE decomposition (Section 4.2) of the same matrix.
+        L = torch.empty((m, m), dtype=A0.dtype, device="cuda")
+        ptimes = []
+        for _ in range(reps):
+            Ad.copy_(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.ple(Ad, e, f, L=L)
+            ptimes.append((time.perf_counter() - t0) * 1e3)
+        row["ple_ms"] = round(float(np.median(ptimes)), 2)
         log(f"echelon {row}")
         res[f"{m}_e{e}"] = row
-        del A0, Ad
+        del A0, Ad, L
     ctx.close()
     return res
 
