@@ -76,8 +76,8 @@ enum {
     GF2E_KERNEL_MFMA_64 = 3,      /* int8 MFMA, 64x64 tiles */
     GF2E_KERNEL_VALU_128 = 4,     /* AND/XOR on packed words, 128x128 tiles */
     GF2E_KERNEL_MFMA_256_W8 = 5,  /* int8 MFMA, 256x256 tiles, 8 waves of 128x64 */
-    GF2E_KERNEL_FP4_256_W8 = 6,   /* fp4 MFMA (0/1 nibbles, exact count in f32), 256x256, k < 2^24 */
-    GF2E_KERNEL_FP4_128 = 7,      /* fp4 MFMA, 128x128 tiles, k < 2^24 */
+    GF2E_KERNEL_FP4_256_W8 = 6,   /* fp4 MFMA (0/1 nibbles, exact count in f32), 256x256, k <= 2^23 */
+    GF2E_KERNEL_FP4_128 = 7,      /* fp4 MFMA, 128x128 tiles, k <= 2^23 */
     GF2E_KERNEL_FP4_128_PLANES = 8 /* as FP4_128 with 128-bit k stages and several planes per
                                       workgroup; the only kernel for products with k <= 128,
                                       which the plain path pads to 128 bits instead of 256 */

@@ -274,7 +274,7 @@ bool kind_supports(int kind, const Plan& p)
 {
     if (p.gK64p % 4) return kind == GEMM_FP4_128x128_PLANES;  // only it steps 128-bit stages
     const bool fp4 = kind == GEMM_FP4_256x256_W8 || kind == GEMM_FP4_128x128 || kind == GEMM_FP4_128x128_PLANES;
-    return !fp4 || p.gK64p * 64 <= (int64_t(1) << 24);
+    return !fp4 || p.gK64p * 64 <= kFp4MaxK;
 }
 
 int supported_kind(int kind, const Plan& p)

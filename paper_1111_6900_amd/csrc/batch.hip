@@ -22,7 +22,7 @@
 namespace gf2e {
 
 namespace {
-// Tile classes: {large, small} x {fp4 (k < 2^24), int8}.
+// Tile classes: {large, small} x {fp4 (k <= 2^23), int8}.
 constexpr int kNumClasses = 4;
 constexpr int kClassKinds[kNumClasses] = {GEMM_FP4_256x256_W8, GEMM_FP4_128x128, GEMM_MFMA_256x256_W8,
                                           GEMM_MFMA_128x128};
@@ -131,7 +131,7 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
         const BatchProduct& d = prods[i];
         if (d.k == 0) continue;
         const int cls = (std::min(d.m, d.n) >= c->batch_threshold ? 0 : 1) +
-                        (d.K64p * 64 <= (int64_t(1) << 24) ? 0 : 2);
+                        (d.K64p * 64 <= kFp4MaxK ? 0 : 2);
         const GemmShape sh = gemm_shape(kClassKinds[cls]);
         const int tm = int(ceil_div(d.m, sh.bm)), tn = int(ceil_div(d.n, sh.bn));
         // Planes of one tile per item: as many as keep an item below

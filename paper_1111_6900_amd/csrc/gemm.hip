@@ -205,9 +205,13 @@ __global__ void reset_counters_kernel(int* counters, int n)
 // FP4 MFMA path (v_mfma_f32_16x16x128_f8f6f4, both operands e2m1, no block
 // scales): every bit becomes a nibble that is 0 or a power of two, chosen per
 // side so that each product of two set bits is exactly 1.0.  Each f32
-// accumulator then holds the exact count of common ones (exact below 2^24;
-// launches with more k are refused), and its low bit is the GF(2) product, as
-// in the int8 path, at twice its MFMA rate.  A stage holds KB consecutive
+// accumulator starts at 2^23 and then holds 2^23 plus the exact count of
+// common ones (exact while the count is at most 2^23; launches with more k
+// are refused), so bit 0 of its bit pattern is the GF(2) product, as in the
+// int8 path, at twice its MFMA rate.  The MFMAs take the B fragment as their
+// first operand, so each accumulator block holds a block of P^T: a lane holds
+// four consecutive columns of one row, which the parity epilogue packs with
+// shifts and a reduction over the four lane groups.  A stage holds KB consecutive
 // 128-bit k-blocks; how each side sits in LDS (packed, split or expanded, see
 // Fp4Side) trades VALU work in the reading waves against LDS bytes.  With
 // operands expanded before the store the kernel was bound by LDS traffic;
@@ -216,7 +220,7 @@ __global__ void reset_counters_kernel(int* counters, int n)
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int64_t kFp4MaxK = int64_t(1) << 24;
+constexpr float kFp4Bias = 8388608.0f;  // 2^23
 
 // fp4 operands occupy the low four dwords of the builtin's 8-dword operand;
 // the upper half is left undefined so no registers are spent on it.
@@ -328,32 +332,43 @@ struct Fp4Side<ROWS, CH, kSplit, BSIDE> {
     }
 };
 
-// Writes the parities of a wave's accumulators as plane words: the same
-// output layout and packing as the int8 tile.
+// Writes the parities of a wave's accumulators as plane words.  Block
+// (i, j) holds P^T: lane (g, l16) register r is row 16 i + l16, column
+// 16 j + 4 g + r of the wave tile, and bit 0 of its pattern is the parity.
+// Each lane packs its 16 bits of a 64-column word (4 per block), shifted to
+// its lane group's columns; an OR over the four lane groups (lanes l16,
+// l16 + 16, + 32, + 48) then gives every lane the word of row 16 i + l16,
+// and lane group g stores the words (i, w) with (i * NW + w) % 4 == g.
 template <int BM, int BN, int WM, int WN>
 __device__ __attribute__((always_inline)) inline void fp4_store_parity(
     const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], uint64_t* __restrict__ Ps,
     int64_t Np, int tile_m, int tile_n, int wr, int wc, int lane)
 {
-    constexpr int FM = MfmaTile<BM, BN, WM, WN>::FM, FN = MfmaTile<BM, BN, WM, WN>::FN;
+    constexpr int FM = MfmaTile<BM, BN, WM, WN>::FM, NW = WN / 64;
     const int64_t ldp = Np / 64;
-    const int rg = lane & 3, rr = (lane >> 2) & 3, wsel = lane >> 4;
+    const int g = lane >> 4, l16 = lane & 15;
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
-        uint64_t word = 0;
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
+        for (int w = 0; w < NW; ++w) {
+            uint32_t half[2] = {0u, 0u};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint64_t bal = __builtin_amdgcn_ballot_w64((int(acc[i][j][r]) & 1) != 0);
-                if (rr == r && wsel == (j >> 2)) word |= ((bal >> (16 * rg)) & 0xFFFFull) << (16 * (j & 3));
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    half[jj >> 1] |= (__float_as_uint(acc[i][4 * w + jj][r]) & 1u) << (16 * (jj & 1) + r);
+            // (shuffled as int: every bit of the pattern is kept)
+            int lo = int(half[0] << (4 * g)), hi = int(half[1] << (4 * g));
+            lo |= __shfl_xor(lo, 16);
+            hi |= __shfl_xor(hi, 16);
+            lo |= __shfl_xor(lo, 32);
+            hi |= __shfl_xor(hi, 32);
+            if (((i * NW + w) & 3) == g) {
+                const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + l16;
+                const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + w;
+                Ps[row * ldp + colw] = uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32);
             }
-        if (lane < 16 * (WN / 64)) {
-            const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + 4 * rg + rr;
-            const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + wsel;
-            Ps[row * ldp + colw] = word;
         }
-    }
 }
 
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
@@ -378,7 +393,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
 
     using Stage = uint64_t[RPT][2 * KB];
     auto gload = [&](int st, Stage& dst) {
@@ -428,7 +443,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
                 for (int j = 0; j < FN; ++j)
                     // Formats 4/4 select e2m1 for both operands; zero scale
                     // operands make the compiler emit the unscaled form.
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0,
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 4, 4, 0,
                                                                                 0, 0, 0);
         }
     };
@@ -507,7 +522,7 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
 
     using Stage = uint64_t[RPT][2 * KB];
     auto gload = [&](int g, Stage& dst) {
@@ -556,7 +571,7 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
                     acc[i][j] =
-                        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[i], b[j], acc[i][j], 4, 4, 0, 0, 0, 0);
+                        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 4, 4, 0, 0, 0, 0);
         }
     };
 
@@ -575,7 +590,7 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
         }
         if (more) store((g & 1) ^ 1, sr);
         __syncthreads();

@@ -35,6 +35,11 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // masks and one shift as an A chunk; the other kernels read B in this order.
 constexpr int b_side_bit(int k) { return (k & 1) ? k : (k ^ 2); }
 
+// Largest k the fp4 product kernels take: their f32 accumulators start at
+// 2^23 and stay exact integers up to 2^24, so counts up to 2^23 are exact.
+// Larger products run on the int8 kernels (exact for any k < 2^31).
+constexpr int64_t kFp4MaxK = int64_t(1) << 23;
+
 // k is padded to whole 256-bit steps, so every product kernel's stages are
 // full and its loads need no bounds guard.
 inline int64_t kwords_padded(int64_t k) { return 4 * ceil_div(k, 256); }
@@ -47,8 +52,8 @@ enum GemmKind : int {
     GEMM_MFMA_64x64 = 3,    // int8 MFMA, 1 wave of 64x64
     GEMM_VALU_128x128 = 4,  // AND/XOR on packed words, 4 waves of 64x64
     GEMM_MFMA_256x256_W8 = 5,  // int8 MFMA, 8 waves of 128x64
-    GEMM_FP4_256x256_W8 = 6,   // fp4 MFMA, 8 waves of 128x64 (k < 2^24)
-    GEMM_FP4_128x128 = 7,      // fp4 MFMA, 4 waves of 64x64 (k < 2^24)
+    GEMM_FP4_256x256_W8 = 6,   // fp4 MFMA, 8 waves of 128x64 (k <= 2^23)
+    GEMM_FP4_128x128 = 7,      // fp4 MFMA, 4 waves of 64x64 (k <= 2^23)
     GEMM_FP4_128x128_PLANES = 8,  // as 7 with 128-bit stages, several planes per workgroup (short k)
     GEMM_NUM_KINDS = 9
 };

@@ -40,7 +40,7 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Tile classes: {large, small} x {fp4 (k < 2^24), int8}.
+// Tile classes: {large, small} x {fp4 (k <= 2^23), int8}.
 constexpr int kNumClasses = 4;
 constexpr int kClassKinds[kNumClasses] = {GEMM_FP4_256x256_W8, GEMM_FP4_128x128, GEMM_MFMA_256x256_W8,
                                           GEMM_MFMA_128x128};
@@ -460,7 +460,7 @@ int gf2e_server_submit(gf2e_server* handle, const gf2e_mat* A, const gf2e_mat* B
     d.Mp = r->plan.Mp; d.Np = r->plan.Np; d.K64p = r->plan.K64p;
     d.e = e; d.T = r->plan.T; d.f = f; d.sid = r->plan.sid;
     r->cls = (std::min(m, n) >= s->ctx->batch_threshold ? 0 : 1) +
-             (r->plan.K64p * 64 <= (int64_t(1) << 24) ? 0 : 2);
+             (r->plan.K64p * 64 <= kFp4MaxK ? 0 : 2);
     const GemmShape sh = gemm_shape(kClassKinds[r->cls]);
     r->tm = int(ceil_div(std::max<int64_t>(m, 1), sh.bm));
     r->tn = int(ceil_div(std::max<int64_t>(n, 1), sh.bn));

@@ -166,10 +166,11 @@ def test_large_k_parity(ctx, k):
 
 
 @pytest.mark.parametrize("kind", [6, 7, 8])
-@pytest.mark.parametrize("k", [2**24 - 64, 2**24 + 1])
+@pytest.mark.parametrize("k", [2**23 - 64, 2**23, 2**23 + 1, 2**24 + 1])
 def test_fp4_count_limit(g, kind, k):
-    """The fp4 kernels keep exact f32 counts up to 2^24; beyond that the plain
-    path falls back to the int8 kernel and stays exact."""
+    """The fp4 kernels keep exact f32 counts (biased by 2^23) for k up to
+    2^23; beyond that the plain path falls back to the int8 kernel and stays
+    exact."""
     c = g.Context(0, kernel=kind)
     A = np.ones((1, k), dtype=np.uint8)
     B = np.ones((k, 1), dtype=np.uint8)
