@@ -75,7 +75,7 @@ def parse_args():
     ap.add_argument("--no-echelon", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-budget-mib", type=int, default=1024,
+    ap.add_argument("--serve-budget-mib", type=int, default=256,
                     help="device memory for resident planes of admitted requests")
     ap.add_argument("--serve-inflight", type=int, default=256)
     ap.add_argument("--serve-bypass", type=int, default=16,
@@ -375,7 +375,7 @@ def echelon_leg(g, torch, workload, log, reps=3):
     return res
 
 
-def serve_leg(g, torch, workload, log, count=10000, budget=1 << 30, max_inflight=256, bypass=16,
+def serve_leg(g, torch, workload, log, count=10000, budget=256 << 20, max_inflight=256, bypass=16,
               load=0.7, verify=True):
     """Served requests: n log-uniform in [64, 4096], e ~ U{2..10}.  A closed-loop
     run (all requests at t=0) gives the saturated rate; an open-loop Poisson
