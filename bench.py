@@ -214,7 +214,9 @@ def batched_leg(g, torch, workload, log, reps=5):
             "speedup": round(plain_ms / batched_ms, 3),
             "batched_element_mac_per_s": emacs / (batched_ms / 1e3),
             "plain_element_mac_per_s": emacs / (plain_ms / 1e3),
-            "work_items": info["items_large"] + info["items_small"],
+            "work_items": info["items_large"] + info["items_small"] + info["items_fused"],
+            "fused_items": info["items_fused"],
+            "fused_recombination": bool(info["fusion"]),
             "tile_threshold": info["threshold"],
             "plane_arena_bytes": info["arena_bytes"]}
 

@@ -134,8 +134,16 @@ int gf2e_mul_batched(gf2e_ctx* ctx, int count, const gf2e_mat* A, const gf2e_mat
 /* Products with min(m, n) >= min_dim take 256x256 tiles in a batch, the rest
  * 128x128 (default 384). */
 int gf2e_set_batch_threshold(gf2e_ctx* ctx, int64_t min_dim);
-/* Autotune that threshold: build and time the batch for each candidate and
- * keep the fastest (the batch is computed several times). */
+/* on = 1 (the default): products of the 128x128 class with e <= 10 and
+ * k <= 2^23 run fused, one work item per tile covering all t(e) planes, whose
+ * epilogue folds each plane's parity words into the e result planes (the
+ * recombination and reduction of Section 5 as one merged map) and clings
+ * them to C; they write no product planes and skip the combining pass.
+ * on = 0: every product writes its planes and is combined afterwards.
+ * Results are the same either way.  GF2E_EINVAL for other values. */
+int gf2e_set_batch_fusion(gf2e_ctx* ctx, int on);
+/* Autotune the threshold and the fusion: build and time the batch for each
+ * candidate pair and keep the fastest (the batch is computed several times). */
 int gf2e_tune_batched(gf2e_ctx* ctx, int count, const gf2e_mat* A, const gf2e_mat* B, gf2e_mat* C,
                       const int* e, const uint32_t* f, void* stream);
 
@@ -145,6 +153,8 @@ typedef struct {
     int graphs_cached;
     int64_t graph_builds;
     int64_t threshold;
+    int64_t items_fused; /* work items of the last batch in the fused class */
+    int fusion;          /* the context's fusion setting */
 } gf2e_batch_stats;
 int gf2e_batch_info(gf2e_ctx* ctx, gf2e_batch_stats* out);
 

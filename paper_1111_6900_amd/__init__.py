@@ -50,7 +50,8 @@ class Geometry(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("items_large", ctypes.c_int64), ("items_small", ctypes.c_int64),
                 ("arena_bytes", ctypes.c_int64), ("graphs_cached", ctypes.c_int),
-                ("graph_builds", ctypes.c_int64), ("threshold", ctypes.c_int64)]
+                ("graph_builds", ctypes.c_int64), ("threshold", ctypes.c_int64),
+                ("items_fused", ctypes.c_int64), ("fusion", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -94,6 +95,7 @@ _SIGS = {
     "gf2e_ple": (_i32, [_vp, _P(Mat), _P(Mat), _i32, _u32, _P(_i64), _vp, _vp]),
     "gf2e_mul_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_set_batch_threshold": (_i32, [_vp, _i64]),
+    "gf2e_set_batch_fusion": (_i32, [_vp, _i32]),
     "gf2e_tune_batched": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gf2e_batch_info": (_i32, [_vp, _P(BatchStats)]),
     "gf2e_server_create": (_i32, [_vp, _P(ServerConfig), _P(_vp)]),
@@ -416,6 +418,10 @@ class Context:
 
     def set_batch_threshold(self, min_dim: int):
         _check(lib().gf2e_set_batch_threshold(self.handle, min_dim), "gf2e_set_batch_threshold")
+
+    def set_batch_fusion(self, on: bool):
+        """gf2e_set_batch_fusion: fused recombination in the batched 128x128 class."""
+        _check(lib().gf2e_set_batch_fusion(self.handle, 1 if on else 0), "gf2e_set_batch_fusion")
 
     def batch_info(self) -> dict:
         st = BatchStats()

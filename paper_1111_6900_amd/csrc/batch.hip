@@ -18,14 +18,40 @@
 #include <vector>
 
 #include "ctx.hpp"
+#include "field.hpp"
 
 namespace gf2e {
 
 namespace {
-// Tile classes: {large, small} x {fp4 (k <= 2^23), int8}.
-constexpr int kNumClasses = 4;
-constexpr int kClassKinds[kNumClasses] = {GEMM_FP4_256x256_W8, GEMM_FP4_128x128, GEMM_MFMA_256x256_W8,
-                                          GEMM_MFMA_128x128};
+// Tile classes: {large, small} x {fp4 (k <= 2^23), int8}, and the fused
+// class: fp4 128x128 tiles of every plane of a product with the
+// recombination in the epilogue (e <= kFusedMaxE).
+constexpr int kNumPlainClasses = 4;
+constexpr int kNumClasses = 5;
+constexpr int kFusedClass = 4;
+constexpr int kClassKinds[kNumPlainClasses] = {GEMM_FP4_256x256_W8, GEMM_FP4_128x128, GEMM_MFMA_256x256_W8,
+                                               GEMM_MFMA_128x128};
+// Tile shape of a class.
+GemmShape class_shape(int cls) { return gemm_shape(cls == kFusedClass ? GEMM_FP4_128x128 : kClassKinds[cls]); }
+
+// omask[s] for the fused epilogue: bit c set when plane product s enters
+// result plane c.  A folded field schedule gives it directly; for a
+// Karatsuba schedule, product s enters coefficient plane d when s is in
+// w[d], and plane d enters result plane c when bit c of x^d mod f is set.
+void result_masks(int e, uint32_t f, int sid, uint32_t* out)
+{
+    const KernelSchedule S = kernel_schedule(e, sid);
+    for (int s = 0; s < S.t; ++s) {
+        if (S.folded) {
+            out[s] = S.c[s];
+            continue;
+        }
+        uint32_t m = 0;
+        for (int d = 0; d < 2 * e - 1; ++d)
+            if ((S.w[d] >> s) & 1u) m ^= x_pow_mod(d, f, e);
+        out[s] = m;
+    }
+}
 }  // namespace
 
 struct BatchGraph {
@@ -36,6 +62,7 @@ struct BatchGraph {
     BatchProduct* d_prods = nullptr;
     WorkItem* d_items = nullptr;
     int* d_counters = nullptr;
+    uint32_t* d_masks = nullptr;  // omask tables of the fused products
     int n_items[kNumClasses] = {};
     int grid[kNumClasses] = {};
     int* d_jobs = nullptr;  // job lists of the slicing and combining launches
@@ -50,6 +77,7 @@ struct BatchGraph {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
         if (d_counters) (void)hipFree(d_counters);
+        if (d_masks) (void)hipFree(d_masks);
         if (d_jobs) (void)hipFree(d_jobs);
         if (d_items) (void)hipFree(d_items);
         if (d_prods) (void)hipFree(d_prods);
@@ -104,8 +132,11 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
         d.slice_a_blocks = k > 0 ? int32_t(pl.Mp / TPB * pl.K64p) : 0;
         d.slice_b_blocks = k > 0 ? int32_t(pl.Np / TPB * pl.K64p) : 0;
         d.combine_blocks = int32_t(ceil_div(m * ceil_div(n, 64), TPB));
+        // Fused: fp4 128x128 class, e small enough for the epilogue's result planes.
+        d.fused = c->batch_fused && k > 0 && e[p] <= kFusedMaxE && pl.K64p * 64 <= kFp4MaxK &&
+                  std::min(m, n) < c->batch_threshold;
         offs.push_back(total);
-        if (k > 0) total += align256(pl.a_bytes) + align256(pl.b_bytes) + align256(pl.p_bytes);
+        if (k > 0) total += align256(pl.a_bytes) + align256(pl.b_bytes) + (d.fused ? 0 : align256(pl.p_bytes));
         prods.push_back(d);
     }
     bg->count = int(prods.size());
@@ -122,7 +153,29 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
         const Plan pl = make_plan(d.e, d.f, d.m, d.k, d.n);
         d.Apl = reinterpret_cast<uint64_t*>(base);
         d.Bpl = reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes));
-        d.P = reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes) + align256(pl.b_bytes));
+        d.P = d.fused ? nullptr : reinterpret_cast<uint64_t*>(base + align256(pl.a_bytes) + align256(pl.b_bytes));
+    }
+    // omask tables of the fused products, one device array.
+    {
+        std::vector<uint32_t> masks;
+        std::vector<int64_t> at(prods.size(), -1);
+        for (size_t i = 0; i < prods.size(); ++i) {
+            if (!prods[i].fused) continue;
+            at[i] = int64_t(masks.size());
+            masks.resize(masks.size() + size_t(prods[i].T));
+            result_masks(prods[i].e, prods[i].f, prods[i].sid, masks.data() + at[i]);
+        }
+        if (!masks.empty()) {
+            if (hipMalloc(&bg->d_masks, masks.size() * sizeof(uint32_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                return GF2E_ENOMEM;
+            }
+            if (hipMemcpy(bg->d_masks, masks.data(), masks.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
+                hipSuccess)
+                return GF2E_EDEVICE;
+            for (size_t i = 0; i < prods.size(); ++i)
+                if (at[i] >= 0) prods[i].omask = bg->d_masks + at[i];
+        }
     }
 
     // Work lists: size class by the smaller output dimension.
@@ -130,10 +183,16 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
     for (size_t i = 0; i < prods.size(); ++i) {
         const BatchProduct& d = prods[i];
         if (d.k == 0) continue;
-        const int cls = (std::min(d.m, d.n) >= c->batch_threshold ? 0 : 1) +
-                        (d.K64p * 64 <= kFp4MaxK ? 0 : 2);
-        const GemmShape sh = gemm_shape(kClassKinds[cls]);
+        const int cls = d.fused ? kFusedClass
+                                : (std::min(d.m, d.n) >= c->batch_threshold ? 0 : 1) +
+                                      (d.K64p * 64 <= kFp4MaxK ? 0 : 2);
+        const GemmShape sh = class_shape(cls);
         const int tm = int(ceil_div(d.m, sh.bm)), tn = int(ceil_div(d.n, sh.bn));
+        if (d.fused) {  // one item per tile, all planes
+            for (int a = 0; a < tm; ++a)
+                for (int b = 0; b < tn; ++b) items[cls].push_back({int32_t(i), 0, a, b, d.T});
+            continue;
+        }
         // Planes of one tile per item: as many as keep an item below
         // kItemKWords k-words in all, so that items stay comparable.
         const int group = int(std::clamp<int64_t>(kItemKWords / d.K64p, 1, d.T));
@@ -154,7 +213,7 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
             });
         }
         bg->n_items[cls] = int(v.size());
-        bg->grid[cls] = v.empty() ? 0 : persistent_grid(kClassKinds[cls]);
+        bg->grid[cls] = v.empty() ? 0 : cls == kFusedClass ? fused_persistent_grid() : persistent_grid(kClassKinds[cls]);
         if (!v.empty() && bg->grid[cls] <= 0) return GF2E_EDEVICE;
     }
 
@@ -193,6 +252,7 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
             for (size_t i = 0; i < prods.size(); ++i) {
                 const BatchProduct& d = prods[i];
                 if ((d.e > kBatchSmallE) != large) continue;
+                if (combine && d.fused) continue;  // its product kernel writes C
                 const int64_t blocks = combine ? d.combine_blocks : int64_t(d.slice_a_blocks) + d.slice_b_blocks;
                 if (blocks == 0) continue;
                 own.push_back(int(i));
@@ -228,8 +288,11 @@ static int build_batch(Ctx* c, int count, const gf2e_mat* A, const gf2e_mat* B, 
     if (err == hipSuccess)
         err = launch_batched_slice(bg->d_prods, bg->slice_jobs, c->d_err, bg->cap);
     for (int cls = 0; cls < kNumClasses && err == hipSuccess; ++cls)
-        err = launch_persistent_gemm(kClassKinds[cls], bg->d_prods, bg->d_items + item_off[cls],
-                                     bg->n_items[cls], bg->d_counters + cls, bg->grid[cls], bg->cap);
+        err = cls == kFusedClass
+                  ? launch_fused_persistent(bg->d_prods, bg->d_items + item_off[cls], bg->n_items[cls],
+                                            bg->d_counters + cls, bg->grid[cls], bg->cap)
+                  : launch_persistent_gemm(kClassKinds[cls], bg->d_prods, bg->d_items + item_off[cls],
+                                           bg->n_items[cls], bg->d_counters + cls, bg->grid[cls], bg->cap);
     if (err == hipSuccess)
         err = launch_batched_combine(bg->d_prods, bg->combine_jobs, bg->cap);
     hipGraph_t graph = nullptr;
@@ -277,6 +340,7 @@ int gf2e_mul_batched(gf2e_ctx* handle, int count, const gf2e_mat* A, const gf2e_
     }
     std::vector<uint8_t> key;
     put(key, c->batch_threshold);
+    put(key, c->batch_fused);
     put(key, count);
     for (int p = 0; p < count; ++p) {
         put(key, A[p]); put(key, B[p]); put(key, C[p]); put(key, e[p]); put(key, f[p]);
@@ -314,6 +378,7 @@ int gf2e_mul_batched(gf2e_ctx* handle, int count, const gf2e_mat* A, const gf2e_
     c->mark_used(s);
     c->last_batch_items[0] = bg->n_items[0] + bg->n_items[2];
     c->last_batch_items[1] = bg->n_items[1] + bg->n_items[3];
+    c->last_batch_items[2] = bg->n_items[kFusedClass];
     c->last_batch_arena = bg->arena_bytes;
     return err == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
 }
@@ -326,12 +391,22 @@ int gf2e_set_batch_threshold(gf2e_ctx* handle, int64_t min_dim)
     return GF2E_OK;
 }
 
+int gf2e_set_batch_fusion(gf2e_ctx* handle, int on)
+{
+    Ctx* c = reinterpret_cast<Ctx*>(handle);
+    if (!c || on < 0 || on > 1) return GF2E_EINVAL;
+    c->batch_fused = on == 1;
+    return GF2E_OK;
+}
+
 int gf2e_batch_info(gf2e_ctx* handle, gf2e_batch_stats* out)
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c || !out) return GF2E_EINVAL;
     out->items_large = c->last_batch_items[0];
     out->items_small = c->last_batch_items[1];
+    out->items_fused = c->last_batch_items[2];
+    out->fusion = c->batch_fused ? 1 : 0;
     out->arena_bytes = c->last_batch_arena;
     out->graphs_cached = int(c->batches.size());
     out->graph_builds = c->batch_builds;
@@ -344,29 +419,43 @@ int gf2e_tune_batched(gf2e_ctx* handle, int count, const gf2e_mat* A, const gf2e
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c) return GF2E_EINVAL;
-    static const int64_t candidates[] = {0, 256, 384, 512, 768, INT64_MAX};
+    // (threshold, fusion) pairs: with fusion on, the products below the
+    // threshold take the fused class, the rest 256x256 tiles.
+    static const int64_t thresholds[] = {0, 256, 384, 512, 768, INT64_MAX};
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceGuard guard(c->device);
     hipEvent_t e0 = c->get_event(), e1 = c->get_event();
     if (!e0 || !e1) return GF2E_EDEVICE;
     int64_t best = c->batch_threshold;
+    bool best_fused = c->batch_fused;
     float best_ms = -1;
-    for (int64_t th : candidates) {
-        c->batch_threshold = th;
-        int rc = gf2e_mul_batched(handle, count, A, B, C, e, f, stream);  // build + warm-up
-        if (rc) { c->batch_threshold = best; return rc; }
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < 3 && rc == GF2E_OK; ++r) rc = gf2e_mul_batched(handle, count, A, B, C, e, f, stream);
-        (void)hipEventRecord(e1, s);
-        if (rc || hipEventSynchronize(e1) != hipSuccess) { c->batch_threshold = best; return rc ? rc : GF2E_EDEVICE; }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = th; }
-        c->release_batches();  // each candidate holds its own plane arena
-    }
+    auto restore = [&] {
+        c->batch_threshold = best;
+        c->batch_fused = best_fused;
+    };
+    for (int fused = 1; fused >= 0; --fused)
+        for (int64_t th : thresholds) {
+            if (fused && th == 0) continue;  // the same as th = 0 without fusion
+            c->batch_threshold = th;
+            c->batch_fused = fused == 1;
+            int rc = gf2e_mul_batched(handle, count, A, B, C, e, f, stream);  // build + warm-up
+            if (rc) { restore(); return rc; }
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && rc == GF2E_OK; ++r) rc = gf2e_mul_batched(handle, count, A, B, C, e, f, stream);
+            (void)hipEventRecord(e1, s);
+            if (rc || hipEventSynchronize(e1) != hipSuccess) { restore(); return rc ? rc : GF2E_EDEVICE; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                best = th;
+                best_fused = fused == 1;
+            }
+            c->release_batches();  // each candidate holds its own plane arena
+        }
     c->event_pool.push_back(e0);
     c->event_pool.push_back(e1);
-    c->batch_threshold = best;
+    restore();
     return GF2E_OK;
 }
 

@@ -94,7 +94,8 @@ struct Ctx {
     std::vector<BatchGraph*> batches;  // cached batched graphs (owned), least recent first
     int64_t batch_threshold = 384;     // min(m, n) at which a product takes 256x256 tiles
     int64_t batch_builds = 0;
-    int64_t last_batch_items[2] = {0, 0};
+    bool batch_fused = true;           // fused recombination for the 128x128 class (e <= kFusedMaxE)
+    int64_t last_batch_items[3] = {0, 0, 0};
     int64_t last_batch_arena = 0;
 
     hipEvent_t get_event();

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <algorithm>
 
+#include "cling.hpp"
 #include "gf2e_internal.hpp"
 
 namespace gf2e {
@@ -289,14 +290,17 @@ __device__ __attribute__((always_inline)) inline void products_before_stores(v4f
 // read).
 enum Fp4Form : int { kPacked = 0, kExpanded = 1, kSplit = 2 };
 
-template <int ROWS, int CH, int FORM, bool BSIDE>
+// PAD: words of padding per chunk row of the packed form.
+template <int ROWS, int CH, int FORM, bool BSIDE, int PAD = 16>
 struct Fp4Side;
 
-template <int ROWS, int CH, bool BSIDE>
-struct Fp4Side<ROWS, CH, kPacked, BSIDE> {
+template <int ROWS, int CH, bool BSIDE, int PAD>
+struct Fp4Side<ROWS, CH, kPacked, BSIDE, PAD> {
     // Row pitch padded by 16 words: the 4 lane groups of one read (same rows,
-    // chunks 4kb..4kb+3) fall on 4 disjoint sets of 16 banks.
-    uint32_t w[2][CH][ROWS + 16];
+    // chunks 4kb..4kb+3) fall on 4 disjoint sets of 16 banks.  Reads in the
+    // grouped column order (fp4_planes_tile) use a pitch padded by 4 words
+    // instead, for the same property.
+    uint32_t w[2][CH][ROWS + PAD];
     __device__ __attribute__((always_inline)) void put(int buf, int c, int r, uint32_t h) { w[buf][c][r] = h; }
     __device__ __attribute__((always_inline)) v8i get(int buf, int c, int r) const
     {
@@ -304,8 +308,8 @@ struct Fp4Side<ROWS, CH, kPacked, BSIDE> {
     }
 };
 
-template <int ROWS, int CH, bool BSIDE>
-struct Fp4Side<ROWS, CH, kExpanded, BSIDE> {
+template <int ROWS, int CH, bool BSIDE, int PAD>
+struct Fp4Side<ROWS, CH, kExpanded, BSIDE, PAD> {
     uint4 w[2][CH][ROWS];
     __device__ __attribute__((always_inline)) void put(int buf, int c, int r, uint32_t h)
     {
@@ -317,8 +321,8 @@ struct Fp4Side<ROWS, CH, kExpanded, BSIDE> {
     }
 };
 
-template <int ROWS, int CH, bool BSIDE>
-struct Fp4Side<ROWS, CH, kSplit, BSIDE> {
+template <int ROWS, int CH, bool BSIDE, int PAD>
+struct Fp4Side<ROWS, CH, kSplit, BSIDE, PAD> {
     // Pitch padded by 16 rows (128 bytes): the two lane groups of a half-wave
     // read fall on disjoint halves of the banks.
     uint2 w[2][CH][ROWS + 16];
@@ -332,20 +336,20 @@ struct Fp4Side<ROWS, CH, kSplit, BSIDE> {
     }
 };
 
-// Writes the parities of a wave's accumulators as plane words.  Block
-// (i, j) holds P^T: lane (g, l16) register r is row 16 i + l16, column
-// 16 j + 4 g + r of the wave tile, and bit 0 of its pattern is the parity.
-// Each lane packs its 16 bits of a 64-column word (4 per block), shifted to
-// its lane group's columns; an OR over the four lane groups (lanes l16,
-// l16 + 16, + 32, + 48) then gives every lane the word of row 16 i + l16,
-// and lane group g stores the words (i, w) with (i * NW + w) % 4 == g.
-template <int BM, int BN, int WM, int WN>
-__device__ __attribute__((always_inline)) inline void fp4_store_parity(
-    const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], uint64_t* __restrict__ Ps,
-    int64_t Np, int tile_m, int tile_n, int wr, int wc, int lane)
+// Parities of a wave's accumulators as plane words.  Block (i, j) holds P^T:
+// lane (g, l16) register r is row 16 i + l16, column 16 j + 4 g + r of the
+// wave tile, and bit 0 of its pattern is the parity.  Each lane packs its 16
+// bits of a 64-column word (4 per block), shifted to its lane group's
+// columns; an OR over the four lane groups (lanes l16, l16 + 16, + 32, + 48)
+// then gives every lane the word of row 16 i + l16, and lane group g owns
+// the words (i, w) with (i * NW + w) % 4 == g: fn(row, word column, word) is
+// called for those.
+template <int BM, int BN, int WM, int WN, class Fn>
+__device__ __attribute__((always_inline)) inline void fp4_parity_words(
+    const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], int tile_m, int tile_n, int wr,
+    int wc, int lane, Fn&& fn)
 {
     constexpr int FM = MfmaTile<BM, BN, WM, WN>::FM, NW = WN / 64;
-    const int64_t ldp = Np / 64;
     const int g = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -366,9 +370,70 @@ __device__ __attribute__((always_inline)) inline void fp4_store_parity(
             if (((i * NW + w) & 3) == g) {
                 const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + l16;
                 const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + w;
-                Ps[row * ldp + colw] = uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32);
+                fn(row, colw, uint64_t(uint32_t(lo)) | (uint64_t(uint32_t(hi)) << 32));
             }
         }
+}
+
+// Stores the parity words of a wave's accumulators into plane Ps.
+template <int BM, int BN, int WM, int WN>
+__device__ __attribute__((always_inline)) inline void fp4_store_parity(
+    const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], uint64_t* __restrict__ Ps,
+    int64_t Np, int tile_m, int tile_n, int wr, int wc, int lane)
+{
+    const int64_t ldp = Np / 64;
+    fp4_parity_words<BM, BN, WM, WN>(acc, tile_m, tile_n, wr, wc, lane,
+                                     [&](int64_t row, int64_t colw, uint64_t word) { Ps[row * ldp + colw] = word; });
+}
+
+// Parity words in the grouped column order of fp4_planes_tile: the B
+// fragment of block j = 4 w + jj at lane x carries column
+// 64 w + 16 (x >> 2) + 4 jj + (x & 3) of the wave tile, so that lane (g, l16)
+// holds, in blocks 4w..4w+3 and registers r, the sixteen consecutive columns
+// 64 w + 16 g + 4 jj + r of row 16 i + l16.  A funnel shift per value moves
+// bit 0 of its pattern in at the top of a word (one instruction per bit), so
+// after sixteen of them bit 16 + 4 jj + r holds column 16 g + 4 jj + r; two
+// exchanges between lane groups then give every lane the whole word.  As in
+// fp4_parity_words, lane group g owns the words (i, w) with
+// (i * NW + w) % 4 == g, and fn(row, word column, word) is called for those.
+template <int BM, int BN, int WM, int WN, class Fn>
+__device__ __attribute__((always_inline)) inline void fp4_parity_words_grouped(
+    const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], int tile_m, int tile_n, int wr,
+    int wc, int lane, Fn&& fn)
+{
+    constexpr int FM = MfmaTile<BM, BN, WM, WN>::FM, NW = WN / 64;
+    const int g = lane >> 4, l16 = lane & 15;
+    const uint32_t down = (g & 1) ? 0u : 16u;  // groups 0 and 2 fill bits 0..15 of their half
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x = __builtin_amdgcn_alignbit(__float_as_uint(acc[i][4 * w + jj][r]), x, 1);
+            const int v = int(x >> down);
+            const int y = v | __shfl_xor(v, 16);  // groups 0, 1: columns 0..31; groups 2, 3: 32..63
+            const int o = __shfl_xor(y, 32);
+            const uint32_t lo = uint32_t(g < 2 ? y : o), hi = uint32_t(g < 2 ? o : y);
+            if (((i * NW + w) & 3) == g) {
+                const int64_t row = int64_t(tile_m) * BM + wr * WM + 16 * i + l16;
+                const int64_t colw = (int64_t(tile_n) * BN + wc * WN) / 64 + w;
+                fn(row, colw, uint64_t(lo) | (uint64_t(hi) << 32));
+            }
+        }
+}
+
+// Stores the parity words of a wave's accumulators (grouped column order).
+template <int BM, int BN, int WM, int WN>
+__device__ __attribute__((always_inline)) inline void fp4_store_parity_grouped(
+    const v4f (&acc)[MfmaTile<BM, BN, WM, WN>::FM][MfmaTile<BM, BN, WM, WN>::FN], uint64_t* __restrict__ Ps,
+    int64_t Np, int tile_m, int tile_n, int wr, int wc, int lane)
+{
+    const int64_t ldp = Np / 64;
+    fp4_parity_words_grouped<BM, BN, WM, WN>(
+        acc, tile_m, tile_n, wr, wc, lane, [&](int64_t row, int64_t colw, uint64_t word) { Ps[row * ldp + colw] = word; });
 }
 
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
@@ -500,22 +565,25 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
 // k-blocks each, K64p a multiple of 2 KB), so that the operands of the next
 // plane load while the current one computes and writes its words.  Products
 // with little k (KB = 1) and the persistent work items (several planes of a
-// tile) are then not bound by one load latency per plane.
-template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
+// tile) are then not bound by one load latency per plane.  After the last
+// stage of plane s, plane_done(s, acc, wr, wc, lane) takes the wave's
+// accumulators (it writes the plane's words, or folds them into results).
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB, class PlaneDone>
 __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
-    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P, int s0, int s1,
-    int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int s0, int s1, int64_t Mp, int64_t Np,
+    int64_t K64p, int tile_m, int tile_n, PlaneDone&& plane_done)
 {
     using TL = MfmaTile<BM, BN, WM, WN>;
     constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
     constexpr int CH = 4 * KB;  // 32-bit chunks per row per stage of KB 128-bit k-blocks
     __shared__ Fp4Side<BM, CH, FA, false> sa;
-    __shared__ Fp4Side<BN, CH, FB, true> sb;
+    __shared__ Fp4Side<BN, CH, FB, true, 4> sb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
     const int nst = int(K64p / (2 * KB));  // stages per plane
     const int G = (s1 - s0) * nst;     // stages of all planes
     static_assert(BM % 64 == 0 && NT % 64 == 0, "a wave stages rows of one side only");
+    static_assert(FB == kPacked, "the grouped column order is laid out for the packed B side");
     static_assert(KB == 1 || KB == 2, "stages of one or two 128-bit k-blocks");
 
     v4f acc[FM][FN];
@@ -565,7 +633,8 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
 #pragma unroll
             for (int i = 0; i < FM; ++i) a[i] = sa.get(buf, 4 * kb + g4, wr * WM + 16 * i + l16);
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = sb.get(buf, 4 * kb + g4, wc * WN + 16 * j + l16);
+            for (int j = 0; j < FN; ++j)  // grouped column order (fp4_parity_words_grouped)
+                b[j] = sb.get(buf, 4 * kb + g4, wc * WN + 64 * (j >> 2) + 16 * (l16 >> 2) + 4 * (j & 3) + (l16 & 3));
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -585,8 +654,7 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
         compute(g & 1);
         products_before_stores(acc);
         if ((g + 1) % nst == 0) {  // last stage of plane s0 + g / nst
-            fp4_store_parity<BM, BN, WM, WN>(acc, P + int64_t(s0 + g / nst) * Mp * (Np / 64), Np, tile_m, tile_n,
-                                             wr, wc, lane);
+            plane_done(s0 + g / nst, acc, wr, wc, lane);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -603,7 +671,12 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
     int64_t Mp, int64_t Np, int64_t K64p)
 {
     const int s0 = int(blockIdx.z) * ppw, s1 = min(T, s0 + ppw);
-    fp4_planes_tile<BM, BN, WM, WN, 1, FA, FB>(Apl, Bpl, P, s0, s1, Mp, Np, K64p, blockIdx.y, blockIdx.x);
+    const int tm = blockIdx.y, tn = blockIdx.x;
+    fp4_planes_tile<BM, BN, WM, WN, 1, FA, FB>(
+        Apl, Bpl, s0, s1, Mp, Np, K64p, tm, tn, [&](int s, const auto& acc, int wr, int wc, int lane) {
+            fp4_store_parity_grouped<BM, BN, WM, WN>(acc, P + int64_t(s) * Mp * (Np / 64), Np, tm, tn, wr, wc,
+                                                     lane);
+        });
 }
 
 // Persistent form: workgroups take (product, planes, tile) items in order
@@ -625,8 +698,81 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
         const WorkItem w = items[it];
         const BatchProduct& P = prods[w.prod];
         // K64p is a multiple of 4 here: stages of two 128-bit k-blocks
-        fp4_planes_tile<BM, BN, WM, WN, 2, FA, FB>(P.Apl, P.Bpl, P.P, w.plane, w.plane + w.nplanes, P.Mp, P.Np,
-                                                   P.K64p, w.tile_m, w.tile_n);
+        uint64_t* Pp = P.P;
+        const int64_t Np = P.Np, pstride = P.Mp * (P.Np / 64);
+        fp4_planes_tile<BM, BN, WM, WN, 2, FA, FB>(
+            P.Apl, P.Bpl, w.plane, w.plane + w.nplanes, P.Mp, Np, P.K64p, w.tile_m, w.tile_n,
+            [&](int s, const auto& acc, int wr, int wc, int lane) {
+                fp4_store_parity_grouped<BM, BN, WM, WN>(acc, Pp + int64_t(s) * pstride, Np, w.tile_m, w.tile_n,
+                                                         wr, wc, lane);
+            });
+    }
+}
+
+// Persistent form with the recombination fused into the epilogue: an item is
+// one tile of every plane of a product.  After each plane, every lane folds
+// the one parity word it owns into the result planes that product feeds
+// (its bits in omask[s]: the merged map of recombination and reduction
+// modulo f, Section 5); the running result planes sit in LDS, one slot per
+// thread and plane.  After the last plane each lane clings its e result
+// words to 64 elements of C.  No product planes are written and no
+// combining pass runs.  For e <= kFusedMaxE.
+template <int BM, int BN, int WM, int WN, int FA, int FB>
+__global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(4))) void gemm_fp4_fused_persistent(
+    const BatchProduct* __restrict__ prods, const WorkItem* __restrict__ items, int nitems,
+    int* __restrict__ counter)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    constexpr int NT = TL::kThreads;
+    static_assert(TL::FM * (WN / 64) == 4, "each lane owns one parity word of a plane");
+    static_assert(kFusedMaxE == 10, "the clinging switch below covers e = 2..10");
+    __shared__ uint64_t res[kFusedMaxE][NT];
+    __shared__ int next;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (it >= nitems) break;
+        const WorkItem w = items[it];
+        const BatchProduct& P = prods[w.prod];
+        const uint32_t* __restrict__ om = P.omask;
+#pragma unroll
+        for (int q = 0; q < kFusedMaxE; ++q) res[q][tid] = 0;  // this thread's slots only
+        fp4_planes_tile<BM, BN, WM, WN, 2, FA, FB>(
+            P.Apl, P.Bpl, 0, P.T, P.Mp, P.Np, P.K64p, w.tile_m, w.tile_n,
+            [&](int s, const auto& acc, int wr, int wc, int lane) {
+                uint64_t mine = 0;
+                fp4_parity_words_grouped<BM, BN, WM, WN>(acc, w.tile_m, w.tile_n, wr, wc, lane,
+                                                         [&](int64_t, int64_t, uint64_t word) { mine = word; });
+                const uint32_t mask = om[s];  // uniform
+#pragma unroll
+                for (int q = 0; q < kFusedMaxE; ++q)
+                    if ((mask >> q) & 1u) res[q][tid] ^= mine;
+            });
+        // The word a lane owns (fp4_parity_words: lane group g owns row
+        // block i = g, so its row in the wave tile is 16 g + l16 = lane).
+        const int wave = tid >> 6, lane = tid & 63;
+        const int64_t row = int64_t(w.tile_m) * BM + (wave / TL::kWavesN) * WM + lane;
+        const int64_t colw = (int64_t(w.tile_n) * BN + (wave % TL::kWavesN) * WN) / 64;
+        if (row < P.m && colw * 64 < P.n) {
+            uint64_t c[kFusedMaxE];
+#pragma unroll
+            for (int q = 0; q < kFusedMaxE; ++q) c[q] = res[q][tid];
+            switch (P.e) {
+                case 2: cling_store<2>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 3: cling_store<3>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 4: cling_store<4>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 5: cling_store<5>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 6: cling_store<6>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 7: cling_store<7>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 8: cling_store<8>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 9: cling_store<9>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                case 10: cling_store<10>(c, P.n, P.C, P.ldc, row, colw, false); break;
+                default: break;
+            }
+        }
     }
 }
 
@@ -840,6 +986,22 @@ hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const Wor
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+int fused_persistent_grid()
+{
+    return blocks_filling_device(gemm_fp4_fused_persistent<128, 128, 64, 64, kPacked, kPacked>,
+                                 MfmaTile<128, 128, 64, 64>::kThreads);
+}
+
+hipError_t launch_fused_persistent(const BatchProduct* prods, const WorkItem* items, int nitems, int* counter,
+                                   int grid, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_fp4_fused_persistent<128, 128, 64, 64, kPacked, kPacked>), dim3(grid),
+                       dim3(MfmaTile<128, 128, 64, 64>::kThreads), 0, s, prods, items, nitems, counter);
     return hipGetLastError();
 }
 

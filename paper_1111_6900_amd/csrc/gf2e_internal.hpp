@@ -107,6 +107,11 @@ struct BatchProduct {
     int32_t slice_a_blocks;  // 256-thread jobs of A-side slicing (0 when k = 0)
     int32_t slice_b_blocks;
     int32_t combine_blocks;
+    // Fused recombination (batched products with e <= kFusedMaxE): omask[s]
+    // has bit c set when product plane s feeds result plane c (T entries,
+    // device memory); the product kernel then writes C itself and P is unused.
+    const uint32_t* omask;
+    int32_t fused;
 };
 
 // One tile of planes plane..plane+nplanes-1 of a product in a persistent
@@ -133,11 +138,19 @@ struct JobList {
 hipError_t launch_batched_slice(const BatchProduct* prods, const JobList (&jobs)[2], int* err, hipStream_t s);
 hipError_t launch_batched_combine(const BatchProduct* prods, const JobList (&jobs)[2], hipStream_t s);
 int batch_threads_per_block();
+// Largest e whose products the fused persistent kernel serves.
+constexpr int kFusedMaxE = 10;
+
 // Persistent grouped products: workgroups take items in order from *counter
 // until it passes nitems.  kind: GEMM_MFMA_256x256_W8 or GEMM_MFMA_128x128.
 hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const WorkItem* items,
                                   int nitems, int* counter, int grid, hipStream_t s);
 int persistent_grid(int kind);  // workgroups that fill the device once
+// The fp4 128x128 persistent kernel with the recombination and clinging in
+// its epilogue: items cover all T planes of a tile of a fused product.
+hipError_t launch_fused_persistent(const BatchProduct* prods, const WorkItem* items, int nitems, int* counter,
+                                   int grid, hipStream_t s);
+int fused_persistent_grid();
 hipError_t launch_reset_counters(int* counters, int n, hipStream_t s);
 
 // count pseudo-random elements of F_{2^e} (uint8 for e <= 8, else uint16).

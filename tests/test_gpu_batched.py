@@ -47,7 +47,8 @@ def test_batch_512_mixed_fields(g):
     ctx = g.Context(0)
     outs = ctx.mul_batched(As, Bs, es, fs)
     info = ctx.batch_info()
-    assert info["graph_builds"] == 1 and info["items_large"] + info["items_small"] > 0
+    assert info["graph_builds"] == 1 and info["items_large"] + info["items_small"] + info["items_fused"] > 0
+    assert info["fusion"] == 1 and info["items_fused"] > 0
     print("checking against the oracle and the plain path", flush=True)
     for p, ((e, f, m, k, n), (a, b)) in enumerate(zip(specs, mats)):
         got = host(outs[p])
@@ -83,6 +84,60 @@ def test_tile_classes_and_shuffled_order(g, threshold, monkeypatch):
     assert ctx.batch_info()["graph_builds"] == 2
     for p in range(len(specs)):
         assert (shuf[p] == ref[p]).all(), p
+    ctx.close()
+
+
+def _other_poly(e, skip):
+    """The smallest irreducible f of degree e other than skip (no field
+    schedule is compiled for it, so it runs the Karatsuba schedule)."""
+    for f in range((1 << e) + 1, 2 << e, 2):
+        if f != skip and oracle.is_irreducible(e, f):
+            return f
+    raise AssertionError(e)
+
+
+def test_fused_and_plain_recombination_agree(g):
+    """Folded field schedules (e = 5..10 with their default f), Karatsuba
+    schedules with the merged reduction map (e = 2..4, and e = 5, 8, 10 with
+    another f), fields above the fused range (e = 11, 12) and ragged, empty and
+    k = 0 products in one batch: with fusion on and off every product equals
+    the oracle, and the two runs give the same bytes."""
+    gen = np.random.default_rng(2718)
+    poly = {**workload.DEFAULT_POLY, **workload.WIDE_POLY}
+    fields = [(e, poly[e]) for e in range(2, 13)]
+    fields += [(e, _other_poly(e, poly[e])) for e in (5, 8, 10)]
+    shapes = [(1, 1, 1), (17, 33, 9), (129, 64, 131), (200, 300, 70), (64, 0, 64), (0, 16, 8), (256, 257, 255),
+              (300, 520, 129)]
+    specs = []
+    for i, (e, f) in enumerate(fields):
+        for j in range(3):
+            specs.append((e, f) + shapes[(i + 3 * j) % len(shapes)])
+    As, Bs, hosts = [], [], []
+    for e, f, m, k, n in specs:
+        a = workload.field_matrix(gen, m, k, e)
+        b = workload.field_matrix(gen, k, n, e)
+        hosts.append((a, b))
+        As.append(to_dev(g, a, e))
+        Bs.append(to_dev(g, b, e))
+    es, fs = [s[0] for s in specs], [s[1] for s in specs]
+    ctx = g.Context(0)
+    ctx.set_batch_threshold(10**9)  # every fp4 product in the 128x128 class
+    results = {}
+    for fusion in (True, False):
+        ctx.set_batch_fusion(fusion)
+        outs = [torch.full((m, n), 7, dtype=g.elem_dtype(e), device="cuda") for e, f, m, k, n in specs]
+        ctx.mul_batched(As, Bs, es, fs, outs=outs)
+        info = ctx.batch_info()
+        assert info["fusion"] == int(fusion)
+        assert (info["items_fused"] > 0) == fusion
+        results[fusion] = [host(o) for o in outs]
+        for (e, f, m, k, n), (a, b), got in zip(specs, hosts, results[fusion]):
+            assert (got == oracle.matmul(a, b, e, f)).all(), (fusion, e, hex(f), m, k, n)
+    for x, y in zip(results[True], results[False]):
+        assert (x == y).all()
+    with pytest.raises(g.GF2EError) as ei:
+        g._check(g.lib().gf2e_set_batch_fusion(ctx.handle, 2))
+    assert ei.value.code == g.EINVAL
     ctx.close()
 
 
@@ -130,8 +185,8 @@ def test_tune_batched_keeps_results(g):
     ctx = g.Context(0)
     outs = [torch.empty((a.size(0), b.size(1)), dtype=a.dtype, device="cuda") for a, b in zip(As, Bs)]
     ctx.tune_batched(As, Bs, es, fs, outs)
-    th = ctx.batch_info()["threshold"]
-    assert th in (0, 256, 384, 512, 768, 2**63 - 1)
+    info = ctx.batch_info()
+    assert info["threshold"] in (0, 256, 384, 512, 768, 2**63 - 1) and info["fusion"] in (0, 1)
     outs = ctx.mul_batched(As, Bs, es, fs, outs=outs)
     for p, ((e, f, m, k, n), (a, b)) in enumerate(zip(specs, mats)):
         assert (host(outs[p]) == oracle.matmul(a, b, e, f)).all(), p
