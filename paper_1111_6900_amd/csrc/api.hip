@@ -625,6 +625,7 @@ void gf2e_destroy(gf2e_ctx* handle)
     if (c->aux) (void)hipFree(c->aux);
     for (auto& kv : c->ftabs) (void)hipFree(kv.second);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->side) (void)hipStreamDestroy(c->side);
     if (c->d_err) (void)hipFree(c->d_err);
     for (int st = 0; st < GF2E_NUM_STAGES; ++st)
         for (auto& pr : c->prof_pending[st]) {

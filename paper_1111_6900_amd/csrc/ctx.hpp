@@ -138,6 +138,10 @@ struct Ctx {
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
     void* ensure_pinned(size_t bytes);
+    // A second stream of the context (default priority, created on first
+    // use): the echelon driver runs the next panel's pivot search on it.
+    hipStream_t side = nullptr;
+    hipStream_t side_stream();
     // Row echelon form in place (reduced when full); host-synchronous.  With
     // ple (full = 0) it also returns the PLE decomposition's L (m x min(m, n),
     // device) and P (m row indices, host).

@@ -14,16 +14,20 @@
 //      That last workgroup (or the probe) eliminates by Gauss-Jordan and
 //      carries each row along as a combination of the pivot rows, so it
 //      also writes W.
-//   2. the pivot rows are moved to rows r..r+rp-1 (only the rows that must
-//      move), and on columns c0..n-1 two products on the bitsliced path
-//      finish the panel:
-//          X1 = W * A[pivot rows]          (in place over the pivot rows)
-//          A[other rows] += G * X1         (G: their original pivot-column
-//                                           entries, zero on the pivot rows)
-//      where the other rows are those below, and those above as well for
-//      the reduced form.  The rows below become zero on the panel (they lie
-//      in the span of the pivot rows there), and the pivot rows become the
-//      reduced rows.
+//   2. the pivot rows Y are moved to rows r..r+rp-1 (only the rows that
+//      must move), and on columns c0..n-1 one product on the bitsliced path
+//      finishes the panel:
+//          A[rows from lo] += H * Y,   H = G * W on the other rows,
+//                                      H = W - I on the pivot rows,
+//      (G: the other rows' original pivot-column entries, zero on the pivot
+//      rows), so that the pivot rows become the reduced rows W * Y and every
+//      other row adds G * (W * Y).  The other rows are those below, and
+//      those above as well for the reduced form (lo = 0).  The rows below
+//      become zero on the panel (they lie in the span of the pivot rows
+//      there).  G * W, and the next panel's columns of the result, come from
+//      tables of multiples (the Newton-John tables of Section 4), so the
+//      next panel's pivot search starts on a side stream before the product
+//      and runs beside it.
 // The reduced row echelon form is unique, so it equals the oracle's result
 // whatever rows are chosen as pivots.
 #include <hip/hip_runtime.h>
@@ -373,6 +377,121 @@ __global__ void scatter_rows_kernel(void* A, int64_t lda, int64_t r, int64_t c0,
     }
 }
 
+// Products with a short inner dimension by tables of multiples (the
+// Newton-John tables of Section 4: all multiples of a row, built once and
+// then read instead of multiplying).  For a k x w block V (k <= kPanel,
+// w <= kPanel; columns from w on count as zero) the table holds, for every
+// row s of V, byte half h of an element (one half for e <= 8, two above)
+// and byte value x,
+//     T[((h * k + s) * 256 + x) * kPanel + c] = (x << 8h) * V[s][c],
+// so that X[i][s] * V[s][:] is the XOR of one table row per half.  Each
+// thread computes one entry by logarithms; values x << 8h outside the
+// field are never looked up and hold zero.
+__global__ __launch_bounds__(256) void grease_build_kernel(const void* V, int64_t ldv, int k, int w, int halves,
+                                                           DevField F, int e, int wide, void* T)
+{
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int c = int(idx % kPanel);
+    const int x = int((idx / kPanel) % 256);
+    const int64_t hs = idx / (int64_t(kPanel) * 256);
+    if (hs >= int64_t(halves) * k) return;
+    const int sr = int(hs % k), h = int(hs / k);
+    const uint32_t xv = uint32_t(x) << (8 * h);
+    const uint32_t v = c < w ? ld_el(V, wide, sr * ldv + c) : 0u;
+    const uint32_t prod = (xv >> e) == 0 ? F.exp[F.log[xv] + F.log[v]] : 0u;
+    st_el(T, wide, idx, prod);
+}
+
+// Applies the table of V (grease_build_kernel) to the rows of X (k columns):
+// for rows i in [x_lo, m) and columns c < kPanel,
+//     out[i][c] = (Cin ? Cin[i][c] : 0) + sum_{s < k} X[i][s] * V[s][c].
+// Cin and Cout have w columns (entries past them count as zero), orig takes
+// columns c < ow (zero beyond; uint16, pitch kPanel); either output may be
+// null.  Rows below x_lo are not written to Cout and copy Cin into orig.  Sixteen threads share a row, each
+// owning four columns; they read the row of X and the table rows that its
+// entries select (64 bytes of a table row per entry and half).
+__global__ __launch_bounds__(256) void grease_apply_kernel(const void* X, int64_t ldx, int k, int64_t m, int64_t x_lo,
+                                                           const void* T, int halves, int wide, const void* Cin,
+                                                           int64_t ldcin, void* Cout, int64_t ldcout, int w,
+                                                           uint16_t* orig, int ow)
+{
+    // The workgroup's sixteen rows of X go through LDS first (each thread
+    // loads four entries), so that every thread then issues all its table
+    // loads at once instead of waiting for each entry of X.
+    __shared__ uint32_t xl[16][kPanel];
+    const int rl = threadIdx.x / 16, c4 = 4 * (threadIdx.x % 16);
+    const int64_t i = int64_t(blockIdx.x) * 16 + rl;
+    const bool live = i < m && i >= x_lo;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xl[rl][c4 + j] = live && c4 + j < k ? ld_el(X, wide, i * ldx + c4 + j) : 0u;
+    __syncthreads();
+    if (i >= m) return;
+    uint32_t acc[4] = {0u, 0u, 0u, 0u};
+    if (Cin)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (c4 + j < w) acc[j] = ld_el(Cin, wide, i * ldcin + c4 + j);
+    if (live) {
+        // 16 table loads in flight, then their XORs
+#pragma unroll
+        for (int s0 = 0; s0 < kPanel; s0 += 16) {
+            if (s0 >= k) break;  // uniform
+            uint2 t[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int sr = s0 + u;
+                const uint32_t x = sr < k ? xl[rl][sr] : 0u;
+                const int srow = sr < k ? sr : 0;  // x = 0 selects a zero row
+                if (wide) {
+                    const uint16_t* T16 = static_cast<const uint16_t*>(T);
+                    const uint2 lo = *reinterpret_cast<const uint2*>(T16 + ((int64_t(srow) * 256 + (x & 0xFFu)) * kPanel + c4));
+                    uint2 hi = make_uint2(0u, 0u);
+                    if (halves > 1)
+                        hi = *reinterpret_cast<const uint2*>(
+                            T16 + ((int64_t(k + srow) * 256 + ((x >> 8) & 0xFFu)) * kPanel + c4));
+                    t[u] = make_uint2(lo.x ^ hi.x, lo.y ^ hi.y);
+                } else {
+                    const uint8_t* T8 = static_cast<const uint8_t*>(T);
+                    t[u] = make_uint2(*reinterpret_cast<const uint32_t*>(T8 + (int64_t(srow) * 256 + x) * kPanel + c4), 0u);
+                }
+            }
+            uint2 sum = make_uint2(0u, 0u);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                sum.x ^= t[u].x;
+                sum.y ^= t[u].y;
+            }
+            if (wide) {
+                acc[0] ^= sum.x & 0xFFFFu;
+                acc[1] ^= sum.x >> 16;
+                acc[2] ^= sum.y & 0xFFFFu;
+                acc[3] ^= sum.y >> 16;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j] ^= (sum.x >> (8 * j)) & 0xFFu;
+            }
+        }
+        if (Cout)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c4 + j < w) st_el(Cout, wide, i * ldcout + c4 + j, acc[j]);
+    }
+    if (orig)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) orig[i * kPanel + c4 + j] = c4 + j < ow ? uint16_t(acc[j]) : 0;
+}
+
+// Rows r..r+k-1 of H (pitch ldh) = V - I for a k x k block V (pitch k): in
+// the one product that finishes a panel, these rows turn the pivot rows Y
+// into V * Y = Y + (V - I) * Y.
+__global__ void pivot_rows_kernel(const void* V, int k, void* H, int64_t ldh, int64_t r, int wide)
+{
+    const int idx = int(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= k * k) return;
+    const int t = idx / k, sc = idx % k;
+    st_el(H, wide, (r + t) * ldh + sc, ld_el(V, wide, idx) ^ (t == sc ? 1u : 0u));
+}
+
 dim3 rows_grid(int64_t rows, int64_t cols)
 {
     return dim3(unsigned(std::min<int64_t>(ceil_div(cols, 256), 64)), unsigned(std::min<int64_t>(rows, 65535)));
@@ -431,6 +550,15 @@ void* Ctx::ensure_pinned(size_t bytes)
     return pinned;
 }
 
+hipStream_t Ctx::side_stream()
+{
+    if (!side && hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        side = nullptr;
+    }
+    return side;
+}
+
 int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_t* pivots, hipStream_t s,
                  PleOut* ple)
 {
@@ -464,8 +592,9 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     const int64_t b_orig = al(m * kPanel * 2), b_cand = al(ceil_div(m, kSelRows) * kPanel * 4),
                   b_state = al(sizeof(PanelState)), b_perm = al((m + 2 * kPanel) * 4),
                   b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz),
-                  b_mv = al(2 * kPanel * n * esz), b_lu = ple ? 3 * b_w : 0;
-    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv + b_lu, s);
+                  b_mv = al(2 * kPanel * n * esz), b_lu = ple ? 3 * b_w : 0,
+                  b_tab = al(2 * int64_t(kPanel) * 256 * kPanel * esz), b_h = al(m * kPanel * esz);
+    int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv + b_lu + b_tab + b_h, s);
     if (rc) return rc;
     uint8_t* base = static_cast<uint8_t*>(aux);
     uint16_t* orig = reinterpret_cast<uint16_t*>(base);
@@ -479,6 +608,10 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     uint8_t* Lk = mvbuf + b_mv;
     uint8_t* Lkinv = Lk + b_w;
     uint8_t* Ukinv = Lkinv + b_w;
+    // Tables of multiples and the coefficient matrix H of each panel's product
+    uint8_t* Tab = mvbuf + b_mv + b_lu;
+    uint8_t* H = Tab + b_tab;
+    const int halves = e > 8 ? 2 : 1;
     std::vector<int64_t> rowid, moved;  // PLE: input index of each current row
     if (ple) {
         rowid.resize(size_t(m));
@@ -499,43 +632,81 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     PanelState* hst_dev = nullptr;
     if (hipHostGetDevicePointer(reinterpret_cast<void**>(&hst_dev), hsp, 0) != hipSuccess || !hst_dev)
         return GF2E_EDEVICE;
-    hipEvent_t sel_done = get_event();
-    if (!sel_done) return GF2E_EDEVICE;
-    struct EventBack {  // back to the pool on every return
+    // The pivot search of the next panel runs on a side stream, beside the
+    // trailing update of the current one (one panel of lookahead): the update
+    // first brings the next panel's columns up to date (event ahead on s),
+    // the search waits for that, and the rest of the update follows on s.
+    hipStream_t s2 = side_stream();
+    hipEvent_t sel_done = get_event(), ahead = get_event();
+    if (!s2 || !sel_done || !ahead) return GF2E_EDEVICE;
+    struct EventBack {  // back to the pool on every return, the side stream drained
         Ctx* c;
-        hipEvent_t ev;
-        ~EventBack() { c->event_pool.push_back(ev); }
-    } event_back{this, sel_done};
+        hipStream_t side;
+        hipEvent_t ev[2];
+        ~EventBack()
+        {
+            (void)hipStreamSynchronize(side);
+            c->event_pool.push_back(ev[0]);
+            c->event_pool.push_back(ev[1]);
+        }
+    } event_back{this, s2, {sel_done, ahead}};
     const PanelState& hs = *hsp;
     std::vector<char> is_piv;
     uint8_t* Ad = static_cast<uint8_t*>(A->data);
     const int64_t lda = A->ld;
     int64_t r = 0;
     const bool lds_tabs = q <= kMaxLdsQ;
+    // A pivot-search launch on the side stream for the panel of bc columns
+    // whose rows start at r0; the final level (one workgroup) also writes the
+    // panel state and W = K^{-1}.
+    auto launch_select = [&]<int ROWS, bool FIN>(int64_t r0, int bc, int64_t nb, int64_t ncand, const int* in,
+                                                 int* out) {
+        constexpr int PARTS = FIN ? kFinalParts : kSelParts;
+        const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * PARTS)};
+        if (lds_tabs)
+            hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, true, FIN>), grid, block, 0, s2, orig, r0, bc, in,
+                               ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
+        else
+            hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, false, FIN>), grid, block, 0, s2, orig, r0, bc, in,
+                               ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
+    };
+    // Probes the first rows from row r0 of the panel at column c0n, on the
+    // side stream after everything enqueued on s so far; copy: copy the panel
+    // first (else the update that precedes has written the copy).
+    auto start_search = [&](int64_t c0n, int64_t r0, bool copy) -> int {
+        const int bcn = int(std::min<int64_t>(kPanel, n - c0n));
+        if (hipEventRecord(ahead, s) != hipSuccess || hipStreamWaitEvent(s2, ahead, 0) != hipSuccess)
+            return GF2E_EDEVICE;
+        if (copy)
+            hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s2,
+                               A->data, lda, m, c0n, bcn, wide, orig);
+        launch_select.template operator()<kProbeRows, true>(r0, bcn, 1, std::min<int64_t>(m - r0, kProbeRows),
+                                                            static_cast<const int*>(nullptr), cand[0]);
+        if (hipGetLastError() != hipSuccess || hipEventRecord(sel_done, s2) != hipSuccess) return GF2E_EDEVICE;
+        return GF2E_OK;
+    };
+    // out = (Cin) + X * V for a k x w block V (k, w <= kPanel) on s, by a
+    // table of V's multiples (grease_build_kernel, grease_apply_kernel); X,
+    // Cin and Cout indexed by absolute row, rows below x_lo left alone.
+    auto grease = [&](const void* V, int64_t ldv, int k, int w, const void* X, int64_t ldx, int64_t x_lo,
+                      const void* Cin, int64_t ldcin, void* Cout, int64_t ldcout, uint16_t* o, int ow) -> int {
+        if (k <= 0) return GF2E_OK;
+        const int64_t entries = int64_t(halves) * k * 256 * kPanel;
+        hipLaunchKernelGGL(grease_build_kernel, dim3(unsigned(ceil_div(entries, 256))), dim3(256), 0, s, V, ldv, k,
+                           w, halves, F, e, wide, static_cast<void*>(Tab));
+        hipLaunchKernelGGL(grease_apply_kernel, dim3(unsigned(ceil_div(m, 16))), dim3(256), 0, s, X, ldx, k, m, x_lo,
+                           static_cast<const void*>(Tab), halves, wide, Cin, ldcin, Cout, ldcout, w, o, ow);
+        return hipGetLastError() == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+    };
+    if (n > 0 && (rc = start_search(0, 0, true))) return rc;
     for (int64_t c0 = 0; c0 < n && r < m; c0 += kPanel) {
         const int bc = int(std::min<int64_t>(kPanel, n - c0));
         const int64_t mr = m - r;
-        // A pivot-search launch; the final level (one workgroup) also writes
-        // the panel state and W = K^{-1}.
-        auto launch_select = [&]<int ROWS, bool FIN>(int64_t nb, int64_t ncand, const int* in, int* out) {
-            constexpr int PARTS = FIN ? kFinalParts : kSelParts;
-            const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * PARTS)};
-            if (lds_tabs)
-                hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, true, FIN>), grid, block, 0, s, orig, r, bc,
-                                   in, ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
-            else
-                hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, false, FIN>), grid, block, 0, s, orig, r, bc,
-                                   in, ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
-        };
-        hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s, A->data, lda,
-                           m, c0, bc, wide, orig);
-        // Probe on the first rows; the whole tournament only when they lack a
-        // pivot in some column and further rows exist.
+        // The probe on the first rows was started by the previous panel; the
+        // whole tournament runs only when they lack a pivot in some column
+        // and further rows exist.
+        if (hipEventSynchronize(sel_done) != hipSuccess) return GF2E_EDEVICE;
         const int64_t probe = std::min<int64_t>(mr, kProbeRows);
-        launch_select.template operator()<kProbeRows, true>(1, probe, static_cast<const int*>(nullptr), cand[0]);
-        if (hipGetLastError() != hipSuccess ||
-            hipEventRecord(sel_done, s) != hipSuccess || hipEventSynchronize(sel_done) != hipSuccess)
-            return GF2E_EDEVICE;
         if (hs.rp < bc && mr > probe) {
             // Tournament levels of kSelRows-row workgroups until at most
             // kProbeRows candidates remain, then the final level on those.
@@ -544,17 +715,23 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             for (int level = 0; ncand > kProbeRows; ++level) {
                 const int64_t nb = ceil_div(ncand, kSelRows);
                 int* out = cand[level & 1];
-                launch_select.template operator()<kSelRows, false>(nb, ncand, in, out);
+                launch_select.template operator()<kSelRows, false>(r, bc, nb, ncand, in, out);
                 in = out;
                 ncand = nb * kPanel;
             }
-            launch_select.template operator()<kProbeRows, true>(1, ncand, in, cand[0]);
+            launch_select.template operator()<kProbeRows, true>(r, bc, 1, ncand, in, cand[0]);
             if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-            if (hipStreamSynchronize(s) != hipSuccess)
+            if (hipStreamSynchronize(s2) != hipSuccess)
                 return GF2E_EDEVICE;
         }
+        // (The host has seen the search complete, so the kernels enqueued on s
+        // from here on read its panel state, W and panel copy.)
         const int rp = hs.rp;
-        if (rp == 0) continue;
+        const bool next = c0 + kPanel < n && r + rp < m;  // a panel follows
+        if (rp == 0) {
+            if (next && (rc = start_search(c0 + kPanel, r, true))) return rc;
+            continue;
+        }
         for (int t = 0; t < rp; ++t)
             if (pivots) pivots[r + t] = c0 + hs.cols[t];
 
@@ -612,6 +789,35 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         }
         if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
 
+        // The product that finishes the panel: A[i][c0..n) += H[i] * Y for
+        // rows i >= lo, where Y is the rp pivot rows (at row r, as they are
+        // now) and H (pitch rp) was set up by the caller: its pivot rows are
+        // V - I, so that the pivot rows become V * Y, and the other rows add
+        // their multiples of V * Y.  Before it, the next panel's copy is
+        // computed from the same H and Y by a table (orig = A + H * Y on the
+        // next panel's columns) and the next pivot search starts on the side
+        // stream (its rows begin at rn).
+        auto finish = [&](int64_t lo, int64_t rn) -> int {
+            uint8_t* Y = Ad + (r * lda + c0) * esz;
+            int rc2;
+            if (next) {
+                const int bcn = int(std::min<int64_t>(kPanel, n - c0 - kPanel));
+                if ((rc2 = grease(Y + kPanel * esz, lda, rp, bcn, H, rp, lo, Ad + (c0 + kPanel) * esz, lda, nullptr, 0,
+                                  orig, bcn)))
+                    return rc2;
+                if ((rc2 = start_search(c0 + kPanel, rn, false))) return rc2;
+            }
+            const gf2e_mat Hm{H + lo * rp * esz, m - lo, rp, rp};
+            const gf2e_mat Ym{Y, rp, nc, lda};
+            gf2e_mat Cm{Ad + (lo * lda + c0) * esz, m - lo, nc, lda};
+            return mul(e, f, &Hm, &Ym, &Cm, s, true);
+        };
+        auto pivot_rows = [&](const void* V) -> int {
+            hipLaunchKernelGGL(pivot_rows_kernel, dim3(unsigned(ceil_div(rp * rp, 256))), dim3(256), 0, s, V, rp,
+                               static_cast<void*>(H), int64_t(rp), r, wide);
+            return hipGetLastError() == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+        };
+
         if (ple) {
             // PLE (Section 4.2): E's rows of this panel are Lk^{-1} times the
             // pivot rows (row echelon form, leading ones), the rows below get
@@ -624,9 +830,9 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                 hipLaunchKernelGGL(panel_lu_kernel<false>, dim3(1), dim3(1024), 0, s, orig, r, st, F, wide,
                                    static_cast<void*>(Lk), static_cast<void*>(Lkinv), static_cast<void*>(Ukinv));
             if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-            const gf2e_mat Li{Lkinv, rp, rp, rp};
-            gf2e_mat Ep{Ad + (r * lda + c0) * esz, rp, nc, lda};
-            if ((rc = mul(e, f, &Li, &Ep, &Ep, s))) return rc;
+            // E_p = Lk^{-1} * (pivot rows), L below = G * Uk^{-1}, and the rows
+            // below lose (L below) * E_p: as one product with H = [Lk^{-1} - I;
+            // (L below) * Lk^{-1}] on rows r..m-1.
             uint8_t* Ld = static_cast<uint8_t*>(ple->L->data);
             const int64_t ldl = ple->L->ld;
             if (hipMemcpy2DAsync(Ld + (r * ldl + r) * esz, size_t(ldl * esz), Lk, size_t(rp * esz),
@@ -634,29 +840,22 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                 return GF2E_EDEVICE;
             const int64_t below = m - r - rp;
             if (below > 0) {
-                const gf2e_mat Gb{G + (r + rp) * rp * esz, below, rp, rp};
-                const gf2e_mat Ui{Ukinv, rp, rp, rp};
-                gf2e_mat Lb{Ld + ((r + rp) * ldl + r) * esz, below, rp, ldl};
-                if ((rc = mul(e, f, &Gb, &Ui, &Lb, s))) return rc;
-                gf2e_mat Cb{Ad + ((r + rp) * lda + c0) * esz, below, nc, lda};
-                if ((rc = mul(e, f, &Lb, &Ep, &Cb, s, true))) return rc;
+                if ((rc = grease(Ukinv, rp, rp, rp, G, rp, r + rp, nullptr, 0, Ld + r * esz, ldl, nullptr, 0)))
+                    return rc;
+                if ((rc = grease(Lkinv, rp, rp, rp, Ld + r * esz, ldl, r + rp, nullptr, 0, H, rp, nullptr, 0)))
+                    return rc;
             }
+            if ((rc = pivot_rows(Lkinv)) || (rc = finish(r, r + rp))) return rc;
             r += rp;
             continue;
         }
-        // X1 = W * (pivot rows), in place over the pivot rows; then every
-        // other row (from r on, or all rows for the reduced form) += G * X1,
-        // where G is zero on the pivot rows, so that they keep X1.  Both
-        // products read their B operand into planes before writing C.
-        const gf2e_mat Wm{W, rp, rp, rp};
-        gf2e_mat X1{Ad + (r * lda + c0) * esz, rp, nc, lda};
-        if ((rc = mul(e, f, &Wm, &X1, &X1, s))) return rc;
+        // H = G * W on the other rows (from lo on), W - I on the pivot rows:
+        // the pivot rows become X1 = W * (pivot rows), every other row adds
+        // G * X1 (G is zero on the pivot rows).
         const int64_t lo = full ? 0 : r;
-        if (m - lo > rp) {
-            const gf2e_mat Gm{G + lo * rp * esz, m - lo, rp, rp};
-            gf2e_mat Cm{Ad + (lo * lda + c0) * esz, m - lo, nc, lda};
-            if ((rc = mul(e, f, &Gm, &X1, &Cm, s, true))) return rc;
-        }
+        if ((rc = grease(W, rp, rp, rp, G, rp, lo, nullptr, 0, H, rp, nullptr, 0)) || (rc = pivot_rows(W)) ||
+            (rc = finish(lo, r + rp)))
+            return rc;
         r += rp;
     }
     *rank = r;
