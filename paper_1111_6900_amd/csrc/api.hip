@@ -355,6 +355,13 @@ int Ctx::exec_plan(const Plan& p, int kind, const void* A, int64_t lda, const vo
                   : launch_slice_cols(p.e, p.sid, B, ldb, p.k, p.n, Bpl, p.Np, p.K64p, d_err, s);
     }
     if (err != hipSuccess) return GF2E_EDEVICE;
+    // Alpha form on an fp4 kernel: the product clings its result into C.
+    const bool fp4 = kind == GEMM_FP4_256x256_W8 || kind == GEMM_FP4_128x128 || kind == GEMM_FP4_128x128_PLANES;
+    if (p.form == kFormAlpha && fp4 && p.e <= kFusedMaxE && p.gK64p * 64 <= kFp4MaxK) {
+        StageTimer t(this, GF2E_STAGE_PRODUCTS, s, timed);
+        err = launch_fused_alpha(p.e, Apl, Bpl, p.m, p.n, p.Mp, p.Np, p.gK64p, C, ldc, acc, s);
+        return err == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+    }
     {
         StageTimer t(this, GF2E_STAGE_PRODUCTS, s, timed);
         err = launch_gemm(kind, p.gT, Apl, Bpl, P, p.m, p.gn, p.Mp, p.gNp, p.gK64p, s);

@@ -568,10 +568,17 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
 // tile) are then not bound by one load latency per plane.  After the last
 // stage of plane s, plane_done(s, acc, wr, wc, lane) takes the wave's
 // accumulators (it writes the plane's words, or folds them into results).
+// Where plane s of each side starts and the word pitch along k: the usual
+// grouped layout has plane s at s * K64p * Mp (A) and s * K64p * Np (B) with
+// pitches Mp and Np.
+struct PlaneAddr {
+    int64_t a_pstride, b_pstride, lda, ldb;
+};
+
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB, class PlaneDone>
-__device__ __attribute__((always_inline)) inline void fp4_planes_tile(
-    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int s0, int s1, int64_t Mp, int64_t Np,
-    int64_t K64p, int tile_m, int tile_n, PlaneDone&& plane_done)
+__device__ __attribute__((always_inline)) inline void fp4_planes_tile_at(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int s0, int s1, PlaneAddr ad, int64_t K64p,
+    int tile_m, int tile_n, PlaneDone&& plane_done)
 {
     using TL = MfmaTile<BM, BN, WM, WN>;
     constexpr int FM = TL::FM, FN = TL::FN, NT = TL::kThreads, RPT = TL::kRowsPerThread;
@@ -595,15 +602,15 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
     using Stage = uint64_t[RPT][2 * KB];
     auto gload = [&](int g, Stage& dst) {
         const int64_t s = s0 + g / nst, st = g % nst;
-        const uint64_t* Ap = Apl + s * K64p * Mp + int64_t(tile_m) * BM;
-        const uint64_t* Bp = Bpl + s * K64p * Np + int64_t(tile_n) * BN;
+        const uint64_t* Ap = Apl + s * ad.a_pstride + int64_t(tile_m) * BM;
+        const uint64_t* Bp = Bpl + s * ad.b_pstride + int64_t(tile_n) * BN;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int r = tid + q * NT;
             if (r < TL::kRows) {
                 const bool isA = r < BM;
                 const uint64_t* src = isA ? Ap + r : Bp + (r - BM);
-                const int64_t ld = isA ? Mp : Np;
+                const int64_t ld = isA ? ad.lda : ad.ldb;
 #pragma unroll
                 for (int w = 0; w < 2 * KB; ++w) dst[q][w] = src[(st * 2 * KB + w) * ld];
             }
@@ -663,6 +670,15 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
         if (more) store((g & 1) ^ 1, sr);
         __syncthreads();
     }
+}
+
+template <int BM, int BN, int WM, int WN, int KB, int FA, int FB, class PlaneDone>
+__device__ __attribute__((always_inline)) inline void fp4_planes_tile(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int s0, int s1, int64_t Mp, int64_t Np,
+    int64_t K64p, int tile_m, int tile_n, PlaneDone&& plane_done)
+{
+    fp4_planes_tile_at<BM, BN, WM, WN, KB, FA, FB>(Apl, Bpl, s0, s1, PlaneAddr{K64p * Mp, K64p * Np, Mp, Np}, K64p,
+                                                   tile_m, tile_n, plane_done);
 }
 
 template <int BM, int BN, int WM, int WN, int FA, int FB>
@@ -773,6 +789,55 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
                 default: break;
             }
         }
+    }
+}
+
+// Alpha-power form with the clinging in the epilogue.  The form's one
+// product has E column blocks (block c of B starts at column c * Np, its
+// words along k at pitch E * Np; A is the same for every block), and column
+// block c of the result is plane c of C.  A workgroup takes a 128 x 128 tile
+// of C and runs the E blocks over it as planes, so that after block c each
+// lane holds plane c of its word of the result (kept in LDS); it then clings
+// the E planes into C (C = A * B, or C += A * B with acc).  No product
+// planes are written and no combining pass runs.  For E <= kFusedMaxE; Kw
+// (words of k) a multiple of 2 KB.
+template <int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_fp4_fused_alpha(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int E, int64_t Mp, int64_t Np, int64_t Kw,
+    int64_t m, int64_t n, void* __restrict__ C, int64_t ldc, int acc)
+{
+    using TL = MfmaTile<128, 128, 64, 64>;
+    static_assert(kFusedMaxE == 10, "the clinging switch below covers e = 2..10");
+    __shared__ uint64_t res[kFusedMaxE][TL::kThreads];
+    const int tid = threadIdx.x, tm = blockIdx.y, tn = blockIdx.x;
+    fp4_planes_tile_at<128, 128, 64, 64, KB, kPacked, kPacked>(
+        Apl, Bpl, 0, E, PlaneAddr{0, Np, Mp, int64_t(E) * Np}, Kw, tm, tn,
+        [&](int c, const auto& a, int wr, int wc, int lane) {
+            uint64_t mine = 0;
+            fp4_parity_words_grouped<128, 128, 64, 64>(a, tm, tn, wr, wc, lane,
+                                                       [&](int64_t, int64_t, uint64_t word) { mine = word; });
+            res[c][tid] = mine;
+        });
+    // the word a lane owns: row 16 g + l16 = lane of its wave's tile
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t row = int64_t(tm) * 128 + (wave / TL::kWavesN) * 64 + lane;
+    const int64_t colw = (int64_t(tn) * 128 + (wave % TL::kWavesN) * 64) / 64;
+    if (row >= m || colw * 64 >= n) return;
+    uint64_t c[kFusedMaxE];
+#pragma unroll
+    for (int q = 0; q < kFusedMaxE; ++q) c[q] = q < E ? res[q][tid] : 0ull;
+    const bool add = acc != 0;
+    switch (E) {
+        case 2: cling_store<2>(c, n, C, ldc, row, colw, add); break;
+        case 3: cling_store<3>(c, n, C, ldc, row, colw, add); break;
+        case 4: cling_store<4>(c, n, C, ldc, row, colw, add); break;
+        case 5: cling_store<5>(c, n, C, ldc, row, colw, add); break;
+        case 6: cling_store<6>(c, n, C, ldc, row, colw, add); break;
+        case 7: cling_store<7>(c, n, C, ldc, row, colw, add); break;
+        case 8: cling_store<8>(c, n, C, ldc, row, colw, add); break;
+        case 9: cling_store<9>(c, n, C, ldc, row, colw, add); break;
+        case 10: cling_store<10>(c, n, C, ldc, row, colw, add); break;
+        default: break;
     }
 }
 
@@ -986,6 +1051,23 @@ hipError_t launch_persistent_gemm(int kind, const BatchProduct* prods, const Wor
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_alpha(int e, const uint64_t* Apl, const uint64_t* Bpl, int64_t m, int64_t n, int64_t Mp,
+                              int64_t Np, int64_t Kw, void* C, int64_t ldc, bool acc, hipStream_t s)
+{
+    const int64_t tm = ceil_div(m, 128), tn = ceil_div(n, 128);
+    if (e < 2 || e > kFusedMaxE || Kw % 2 || Kw * 64 > kFp4MaxK || tm * 128 > Mp || tn * 128 > Np)
+        return hipErrorInvalidValue;
+    if (m == 0 || n == 0) return hipSuccess;
+    const dim3 grid{unsigned(tn), unsigned(tm)}, block{unsigned(MfmaTile<128, 128, 64, 64>::kThreads)};
+    if (Kw % 4 == 0)
+        hipLaunchKernelGGL(gemm_fp4_fused_alpha<2>, grid, block, 0, s, Apl, Bpl, e, Mp, Np, Kw, m, n, C, ldc,
+                           acc ? 1 : 0);
+    else
+        hipLaunchKernelGGL(gemm_fp4_fused_alpha<1>, grid, block, 0, s, Apl, Bpl, e, Mp, Np, Kw, m, n, C, ldc,
+                           acc ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -151,6 +151,11 @@ int persistent_grid(int kind);  // workgroups that fill the device once
 hipError_t launch_fused_persistent(const BatchProduct* prods, const WorkItem* items, int nitems, int* counter,
                                    int grid, hipStream_t s);
 int fused_persistent_grid();
+// Alpha-power form (plan with E = e column blocks, Kw words of k) with the
+// clinging fused into the fp4 product: C = A * B (or C += A * B) straight
+// from the operand planes.  e <= kFusedMaxE, Kw even and Kw * 64 <= kFp4MaxK.
+hipError_t launch_fused_alpha(int e, const uint64_t* Apl, const uint64_t* Bpl, int64_t m, int64_t n, int64_t Mp,
+                              int64_t Np, int64_t Kw, void* C, int64_t ldc, bool acc, hipStream_t s);
 hipError_t launch_reset_counters(int* counters, int n, hipStream_t s);
 
 // count pseudo-random elements of F_{2^e} (uint8 for e <= 8, else uint16).
