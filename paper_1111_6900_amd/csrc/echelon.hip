@@ -592,7 +592,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     const int64_t b_orig = al(m * kPanel * 2), b_cand = al(ceil_div(m, kSelRows) * kPanel * 4),
                   b_state = al(sizeof(PanelState)), b_perm = al((m + 2 * kPanel) * 4),
                   b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz),
-                  b_mv = al(2 * kPanel * n * esz), b_lu = ple ? 3 * b_w : 0,
+                  b_mv = al(2 * kPanel * n * esz), b_lu = ple ? 6 * b_w : 0,
                   b_tab = al(2 * int64_t(kPanel) * 256 * kPanel * esz), b_h = al(m * kPanel * esz);
     int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv + b_lu + b_tab + b_h, s);
     if (rc) return rc;
@@ -604,10 +604,11 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     uint8_t* W = base + b_orig + 2 * b_cand + b_state + b_perm;
     uint8_t* G = W + b_w;
     uint8_t* mvbuf = G + b_g;
-    // PLE: the panel's Lk, Lk^{-1} and Uk^{-1} (panel_lu_kernel)
-    uint8_t* Lk = mvbuf + b_mv;
-    uint8_t* Lkinv = Lk + b_w;
-    uint8_t* Ukinv = Lkinv + b_w;
+    // PLE: the panel's Lk, Lk^{-1} and Uk^{-1} (panel_lu_kernel), two sets:
+    // the next panel's are computed on the side stream while this panel's
+    // are still read.
+    uint8_t* lu_sets = mvbuf + b_mv;
+    auto lu_set = [&](int64_t c0p, int which) { return lu_sets + (((c0p / kPanel) & 1) * 3 + which) * b_w; };
     // Tables of multiples and the coefficient matrix H of each panel's product
     uint8_t* Tab = mvbuf + b_mv + b_lu;
     uint8_t* H = Tab + b_tab;
@@ -670,6 +671,15 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, false, FIN>), grid, block, 0, s2, orig, r0, bc, in,
                                ncand, out, st, hst_dev, F, wide, static_cast<void*>(W));
     };
+    // PLE: the LU factors of the pivot block of the panel at column c0n (rows
+    // from r0) on the side stream, after its pivot search.
+    auto launch_lu = [&](int64_t c0n, int64_t r0) {
+        void *lk = lu_set(c0n, 0), *li = lu_set(c0n, 1), *ui = lu_set(c0n, 2);
+        if (lds_tabs)
+            hipLaunchKernelGGL(panel_lu_kernel<true>, dim3(1), dim3(1024), 0, s2, orig, r0, st, F, wide, lk, li, ui);
+        else
+            hipLaunchKernelGGL(panel_lu_kernel<false>, dim3(1), dim3(1024), 0, s2, orig, r0, st, F, wide, lk, li, ui);
+    };
     // Probes the first rows from row r0 of the panel at column c0n, on the
     // side stream after everything enqueued on s so far; copy: copy the panel
     // first (else the update that precedes has written the copy).
@@ -682,6 +692,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                                A->data, lda, m, c0n, bcn, wide, orig);
         launch_select.template operator()<kProbeRows, true>(r0, bcn, 1, std::min<int64_t>(m - r0, kProbeRows),
                                                             static_cast<const int*>(nullptr), cand[0]);
+        if (ple) launch_lu(c0n, r0);
         if (hipGetLastError() != hipSuccess || hipEventRecord(sel_done, s2) != hipSuccess) return GF2E_EDEVICE;
         return GF2E_OK;
     };
@@ -720,6 +731,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                 ncand = nb * kPanel;
             }
             launch_select.template operator()<kProbeRows, true>(r, bc, 1, ncand, in, cand[0]);
+            if (ple) launch_lu(c0, r);  // again, on the final pivots
             if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
             if (hipStreamSynchronize(s2) != hipSuccess)
                 return GF2E_EDEVICE;
@@ -823,13 +835,8 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             // pivot rows (row echelon form, leading ones), the rows below get
             // the multipliers G Uk^{-1} in L and lose their multiples of E's
             // rows; the rows above keep their entries (E is not reduced).
-            if (lds_tabs)
-                hipLaunchKernelGGL(panel_lu_kernel<true>, dim3(1), dim3(1024), 0, s, orig, r, st, F, wide,
-                                   static_cast<void*>(Lk), static_cast<void*>(Lkinv), static_cast<void*>(Ukinv));
-            else
-                hipLaunchKernelGGL(panel_lu_kernel<false>, dim3(1), dim3(1024), 0, s, orig, r, st, F, wide,
-                                   static_cast<void*>(Lk), static_cast<void*>(Lkinv), static_cast<void*>(Ukinv));
-            if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
+            // (Lk, Lk^{-1} and Uk^{-1} came with the pivot search.)
+            uint8_t *Lk = lu_set(c0, 0), *Lkinv = lu_set(c0, 1), *Ukinv = lu_set(c0, 2);
             // E_p = Lk^{-1} * (pivot rows), L below = G * Uk^{-1}, and the rows
             // below lose (L below) * E_p: as one product with H = [Lk^{-1} - I;
             // (L below) * Lk^{-1}] on rows r..m-1.
