@@ -282,17 +282,25 @@ __global__ void gather_pivot_columns_kernel(const uint16_t* orig, int64_t r, int
 // Lk is lower triangular with the pivots on its diagonal, Uk unit upper
 // triangular.  Writes Lk, Lk^{-1} and Uk^{-1} (rp x rp, pitch rp): the
 // panel's rows of E are Lk^{-1} times the pivot rows, and a row below with
-// pivot-column entries g gets the multipliers g Uk^{-1} in L.  One
-// workgroup; each step updates its whole trailing block in parallel.
+// pivot-column entries g gets the multipliers g Uk^{-1} in L.
+//
+// One workgroup eliminates [K | I] forward, one barrier per step: step t
+// adds (K[i][t] / K[t][t]) times row t to every row i below, on the columns
+// right of t and on the right half, leaving column t (Lk's column) and row t
+// unscaled.  Afterwards Lk is the left half's lower triangle, and row t of
+// the right half over K[t][t] is row t of Lk^{-1} (the same row operations,
+// scaled, take K to Uk).  Uk^{-1} = K^{-1} Lk, with K^{-1} = W from the
+// pivot search.
 template <bool LDS_TABS>
 __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, int64_t r, const PanelState* st,
-                                                        DevField F, int wide, void* Lk, void* Linv, void* Uinv)
+                                                        DevField F, int wide, const void* W, void* Lk, void* Linv,
+                                                        void* Uinv)
 {
-    constexpr int NT = 1024, P1 = kPanel + 1;
+    constexpr int NT = 1024, PX = 2 * kPanel + 1;
     __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
     __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
-    __shared__ uint16_t K[kPanel * P1];
-    __shared__ uint16_t X[kPanel * P1];
+    __shared__ uint16_t X[kPanel * PX];  // [K | I], then [Lk, Uk | Lk^{-1} scaled]
+    __shared__ uint16_t Wl[kPanel * kPanel];
     const int tid = threadIdx.x, q = int(F.q), rp = st->rp;
     if constexpr (LDS_TABS) {
         for (int k = tid; k <= 4 * q; k += NT) sexp[k] = F.exp[k];
@@ -300,58 +308,35 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
     }
     const uint16_t* ex = LDS_TABS ? sexp : F.exp;
     const uint32_t* lg = LDS_TABS ? slog : F.log;
-    auto mul = [&](uint32_t a, uint32_t b) { return uint32_t(ex[lg[a] + lg[b]]); };
     for (int idx = tid; idx < rp * rp; idx += NT) {
         const int t = idx / rp, c = idx % rp;
-        K[t * P1 + c] = orig[(r + st->rows[t]) * kPanel + st->cols[c]];
+        X[t * PX + c] = orig[(r + st->rows[t]) * kPanel + st->cols[c]];
+        X[t * PX + kPanel + c] = t == c ? 1 : 0;
+        Wl[idx] = uint16_t(ld_el(W, wide, idx));
     }
     __syncthreads();
-    // Lk in K's lower triangle (diagonal included), Uk in its strict upper one
     for (int t = 0; t < rp; ++t) {
-        const uint32_t inv = ex[q - int(lg[K[t * P1 + t]])];
-        for (int c = t + 1 + tid; c < rp; c += NT) K[t * P1 + c] = uint16_t(mul(K[t * P1 + c], inv));
-        __syncthreads();
-        const int w = rp - t - 1;
-        for (int idx = tid; idx < w * w; idx += NT) {
-            const int i = t + 1 + idx / w, c = t + 1 + idx % w;
-            K[i * P1 + c] ^= uint16_t(mul(K[i * P1 + t], K[t * P1 + c]));
+        const uint32_t inv = uint32_t(q) - lg[X[t * PX + t]];
+        const int wl = rp - t - 1, w = wl + t + 1;  // columns t+1..rp-1, then right-half columns 0..t
+        for (int idx = tid; idx < wl * w; idx += NT) {
+            const int i = t + 1 + idx / w, cc = idx % w;
+            const int c = cc < wl ? t + 1 + cc : kPanel + (cc - wl);
+            const uint32_t a = X[i * PX + t];
+            const uint32_t f = ex[lg[a] + inv];  // K[i][t] / K[t][t]
+            X[i * PX + c] ^= uint16_t(ex[lg[f] + lg[X[t * PX + c]]]);
         }
         __syncthreads();
     }
     for (int idx = tid; idx < rp * rp; idx += NT) {
         const int t = idx / rp, c = idx % rp;
-        st_el(Lk, wide, idx, c <= t ? K[t * P1 + c] : 0u);
-        X[t * P1 + c] = t == c ? 1 : 0;
+        const uint32_t inv = uint32_t(q) - lg[X[t * PX + t]];
+        st_el(Lk, wide, idx, c <= t ? X[t * PX + c] : 0u);
+        st_el(Linv, wide, idx, ex[lg[X[t * PX + kPanel + c]] + inv]);
+        // Uk^{-1}[t][c] = sum_s W[t][s] Lk[s][c], Lk[s][c] = 0 for s < c
+        uint32_t u = 0;
+        for (int sr = c; sr < rp; ++sr) u ^= ex[lg[Wl[t * rp + sr]] + lg[X[sr * PX + c]]];
+        st_el(Uinv, wide, idx, u);
     }
-    __syncthreads();
-    // Lk^{-1}: row t of X scaled by 1 / Lk[t][t], then removed from the rows below
-    for (int t = 0; t < rp; ++t) {
-        const uint32_t inv = ex[q - int(lg[K[t * P1 + t]])];
-        for (int c = tid; c <= t; c += NT) X[t * P1 + c] = uint16_t(mul(X[t * P1 + c], inv));
-        __syncthreads();
-        const int below = rp - t - 1;
-        for (int idx = tid; idx < below * (t + 1); idx += NT) {
-            const int i = t + 1 + idx / (t + 1), c = idx % (t + 1);
-            X[i * P1 + c] ^= uint16_t(mul(K[i * P1 + t], X[t * P1 + c]));
-        }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < rp * rp; idx += NT) {
-        const int t = idx / rp, c = idx % rp;
-        st_el(Linv, wide, idx, X[t * P1 + c]);
-        X[t * P1 + c] = t == c ? 1 : 0;
-    }
-    __syncthreads();
-    // Uk^{-1} (unit diagonal): row t of X removed from the rows above, last row first
-    for (int t = rp - 1; t >= 0; --t) {
-        const int cols = rp - t;
-        for (int idx = tid; idx < t * cols; idx += NT) {
-            const int i = idx / cols, c = t + idx % cols;
-            X[i * P1 + c] ^= uint16_t(mul(K[i * P1 + t], X[t * P1 + c]));
-        }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < rp * rp; idx += NT) st_el(Uinv, wide, idx, X[(idx / rp) * P1 + idx % rp]);
 }
 
 // Row moves of one panel on columns c0..c0+cols-1: position r + moves[j]
@@ -675,10 +660,13 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     // from r0) on the side stream, after its pivot search.
     auto launch_lu = [&](int64_t c0n, int64_t r0) {
         void *lk = lu_set(c0n, 0), *li = lu_set(c0n, 1), *ui = lu_set(c0n, 2);
+        const void* w = W;
         if (lds_tabs)
-            hipLaunchKernelGGL(panel_lu_kernel<true>, dim3(1), dim3(1024), 0, s2, orig, r0, st, F, wide, lk, li, ui);
+            hipLaunchKernelGGL(panel_lu_kernel<true>, dim3(1), dim3(1024), 0, s2, orig, r0, st, F, wide, w, lk, li,
+                               ui);
         else
-            hipLaunchKernelGGL(panel_lu_kernel<false>, dim3(1), dim3(1024), 0, s2, orig, r0, st, F, wide, lk, li, ui);
+            hipLaunchKernelGGL(panel_lu_kernel<false>, dim3(1), dim3(1024), 0, s2, orig, r0, st, F, wide, w, lk, li,
+                               ui);
     };
     // Probes the first rows from row r0 of the panel at column c0n, on the
     // side stream after everything enqueued on s so far; copy: copy the panel
