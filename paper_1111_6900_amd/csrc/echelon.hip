@@ -299,12 +299,15 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
     constexpr int NT = 1024, PX = 2 * kPanel + 1;
     __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
     __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
-    __shared__ uint16_t X[kPanel * PX];  // [K | I], then [Lk, Uk | Lk^{-1} scaled]
-    __shared__ uint16_t Wl[kPanel * kPanel];
+    __shared__ uint16_t X[kPanel * PX];         // [K | I], then [Lk, U' | M]
+    __shared__ uint32_t lw[kPanel * kPanel];    // logs of W, then of Lk (for Uk^{-1})
+    __shared__ uint32_t lrow[2 * kPanel];       // step t: logs of row t
+    __shared__ uint32_t lcol[kPanel];           // step t: logs of K[i][t] / K[t][t]
     const int tid = threadIdx.x, q = int(F.q), rp = st->rp;
     if constexpr (LDS_TABS) {
         for (int k = tid; k <= 4 * q; k += NT) sexp[k] = F.exp[k];
         for (int k = tid; k <= q; k += NT) slog[k] = F.log[k];
+        __syncthreads();
     }
     const uint16_t* ex = LDS_TABS ? sexp : F.exp;
     const uint32_t* lg = LDS_TABS ? slog : F.log;
@@ -312,29 +315,42 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
         const int t = idx / rp, c = idx % rp;
         X[t * PX + c] = orig[(r + st->rows[t]) * kPanel + st->cols[c]];
         X[t * PX + kPanel + c] = t == c ? 1 : 0;
-        Wl[idx] = uint16_t(ld_el(W, wide, idx));
     }
     __syncthreads();
     for (int t = 0; t < rp; ++t) {
-        const uint32_t inv = uint32_t(q) - lg[X[t * PX + t]];
-        const int wl = rp - t - 1, w = wl + t + 1;  // columns t+1..rp-1, then right-half columns 0..t
+        const int wl = rp - t - 1;  // left columns t+1..rp-1; right-half columns 0..t
+        if (tid < wl + t + 1) {
+            const int c = tid < wl ? t + 1 + tid : kPanel + (tid - wl);
+            lrow[c] = lg[X[t * PX + c]];
+        } else if (tid >= 128 && tid - 128 < wl) {
+            const int i = t + 1 + (tid - 128);
+            const uint32_t inv = uint32_t(q) - lg[X[t * PX + t]];
+            lcol[i] = lg[ex[lg[X[i * PX + t]] + inv]];
+        }
+        __syncthreads();
+        const int w = wl + t + 1;
         for (int idx = tid; idx < wl * w; idx += NT) {
             const int i = t + 1 + idx / w, cc = idx % w;
             const int c = cc < wl ? t + 1 + cc : kPanel + (cc - wl);
-            const uint32_t a = X[i * PX + t];
-            const uint32_t f = ex[lg[a] + inv];  // K[i][t] / K[t][t]
-            X[i * PX + c] ^= uint16_t(ex[lg[f] + lg[X[t * PX + c]]]);
+            X[i * PX + c] ^= ex[lcol[i] + lrow[c]];
         }
         __syncthreads();
     }
     for (int idx = tid; idx < rp * rp; idx += NT) {
         const int t = idx / rp, c = idx % rp;
         const uint32_t inv = uint32_t(q) - lg[X[t * PX + t]];
-        st_el(Lk, wide, idx, c <= t ? X[t * PX + c] : 0u);
+        const uint32_t l = c <= t ? X[t * PX + c] : 0u;
+        st_el(Lk, wide, idx, l);
         st_el(Linv, wide, idx, ex[lg[X[t * PX + kPanel + c]] + inv]);
-        // Uk^{-1}[t][c] = sum_s W[t][s] Lk[s][c], Lk[s][c] = 0 for s < c
+        lw[idx] = lg[l];
+    }
+    __syncthreads();
+    // Uk^{-1}[t][c] = sum_s W[t][s] Lk[s][c] (Lk[s][c] = 0 for s < c)
+    for (int idx = tid; idx < rp * rp; idx += NT) {
+        const int t = idx / rp, c = idx % rp;
         uint32_t u = 0;
-        for (int sr = c; sr < rp; ++sr) u ^= ex[lg[Wl[t * rp + sr]] + lg[X[sr * PX + c]]];
+#pragma unroll 8
+        for (int sr = c; sr < rp; ++sr) u ^= ex[lg[ld_el(W, wide, int64_t(t) * rp + sr)] + lw[sr * rp + c]];
         st_el(Uinv, wide, idx, u);
     }
 }
