@@ -108,6 +108,28 @@ def test_alpha_form_every_kernel(g, e, kind):
     c.close()
 
 
+@pytest.mark.parametrize("e,f", ALL_E + [(5, 0x29), (8, 0x11B), (11, 0x805)])
+def test_alpha_form_clinging_in_the_product(g, e, f):
+    """The alpha form on an fp4 kernel clings its result in the product's
+    epilogue (e <= 10; e = 11 takes the separate combining pass): C = A*B and
+    C += A*B against the oracle, for k of one word per block (even and odd e),
+    two words, and several 256-bit stages, with ragged m and n."""
+    c = g.Context(0, kernel=g.KERNEL_FP4_128)
+    c.set_form(g.FORM_ALPHA)
+    gen = np.random.default_rng(e * 7 + f)
+    for m, k, n in [(1, 1, 1), (70, 33, 150), (129, 64, 257), (200, 65, 64), (256, 128, 131), (131, 300, 190)]:
+        assert c.chosen_form(e, f, m, k, n) == g.FORM_ALPHA
+        A = workload.field_matrix(gen, m, k, e)
+        B = workload.field_matrix(gen, k, n, e)
+        want = oracle.matmul(A, B, e, f)
+        assert (gpu_mul(c, A, B, e, f) == want).all(), (m, k, n)
+        C0 = workload.field_matrix(gen, m, n, e)
+        Cd = dev(C0, e)
+        c.mul_add(dev(A, e), dev(B, e), Cd, e, f)
+        assert (host(Cd) == (C0 ^ want)).all(), (m, k, n)
+    c.close()
+
+
 def test_alpha_form_falls_back_from_fp4_past_its_count_limit(g):
     """The alpha form's product has e*k bits of inner dimension, so the fp4
     kernels (exact below 2^24) are replaced by the int8 kernel earlier."""
