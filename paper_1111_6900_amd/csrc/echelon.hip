@@ -300,7 +300,8 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
     __shared__ uint16_t sexp[LDS_TABS ? kLdsExp : 1];
     __shared__ uint32_t slog[LDS_TABS ? kMaxLdsQ + 1 : 1];
     __shared__ uint16_t X[kPanel * PX];         // [K | I], then [Lk, U' | M]
-    __shared__ uint32_t lw[kPanel * kPanel];    // logs of W, then of Lk (for Uk^{-1})
+    __shared__ uint32_t lw[kPanel * kPanel];    // logs of Lk (for Uk^{-1})
+    __shared__ uint32_t lwi[kPanel * kPanel];   // logs of W = K^{-1}
     __shared__ uint32_t lrow[2 * kPanel];       // step t: logs of row t
     __shared__ uint32_t lcol[kPanel];           // step t: logs of K[i][t] / K[t][t]
     const int tid = threadIdx.x, q = int(F.q), rp = st->rp;
@@ -315,6 +316,7 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
         const int t = idx / rp, c = idx % rp;
         X[t * PX + c] = orig[(r + st->rows[t]) * kPanel + st->cols[c]];
         X[t * PX + kPanel + c] = t == c ? 1 : 0;
+        lwi[idx] = lg[ld_el(W, wide, idx)];
     }
     __syncthreads();
     for (int t = 0; t < rp; ++t) {
@@ -328,11 +330,14 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
             lcol[i] = lg[ex[lg[X[i * PX + t]] + inv]];
         }
         __syncthreads();
-        const int w = wl + t + 1;
-        for (int idx = tid; idx < wl * w; idx += NT) {
-            const int i = t + 1 + idx / w, cc = idx % w;
-            const int c = cc < wl ? t + 1 + cc : kPanel + (cc - wl);
-            X[i * PX + c] ^= ex[lcol[i] + lrow[c]];
+        // thread (row group, column): column tc of the step's w <= kPanel
+        // columns, rows t + 1 + tr, t + 17, ... (independent updates)
+        const int tc = tid % kPanel, tr = tid / kPanel;
+        if (tc < wl + t + 1) {
+            const int c = tc < wl ? t + 1 + tc : kPanel + (tc - wl);
+            const uint32_t lr = lrow[c];
+#pragma unroll 4
+            for (int i = t + 1 + tr; i < rp; i += NT / kPanel) X[i * PX + c] ^= ex[lcol[i] + lr];
         }
         __syncthreads();
     }
@@ -350,7 +355,7 @@ __global__ __launch_bounds__(1024) void panel_lu_kernel(const uint16_t* orig, in
         const int t = idx / rp, c = idx % rp;
         uint32_t u = 0;
 #pragma unroll 8
-        for (int sr = c; sr < rp; ++sr) u ^= ex[lg[ld_el(W, wide, int64_t(t) * rp + sr)] + lw[sr * rp + c]];
+        for (int sr = c; sr < rp; ++sr) u ^= ex[lwi[t * rp + sr] + lw[sr * rp + c]];
         st_el(Uinv, wide, idx, u);
     }
 }
