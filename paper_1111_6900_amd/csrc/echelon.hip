@@ -392,20 +392,28 @@ __global__ void scatter_rows_kernel(void* A, int64_t lda, int64_t r, int64_t c0,
 //     T[((h * k + s) * 256 + x) * kPanel + c] = (x << 8h) * V[s][c],
 // so that X[i][s] * V[s][:] is the XOR of one table row per half.  Each
 // thread computes one entry by logarithms; values x << 8h outside the
-// field are never looked up and hold zero.
-__global__ __launch_bounds__(256) void grease_build_kernel(const void* V, int64_t ldv, int k, int w, int halves,
-                                                           DevField F, int e, int wide, void* T)
+// field are never looked up and hold zero.  One launch builds the tables of
+// two blocks V1 (into T1) and V2 (into T2, when V2 is set) with the same k.
+__global__ __launch_bounds__(256) void grease_build_kernel(const void* V1, int64_t ldv1, int w1, void* T1,
+                                                           const void* V2, int64_t ldv2, int w2, void* T2, int k,
+                                                           int halves, DevField F, int e, int wide)
 {
-    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t entries = int64_t(halves) * k * 256 * kPanel;
+    int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const bool second = idx >= entries;
+    if (second) idx -= entries;
+    if (idx >= entries || (second && !V2)) return;
+    const void* V = second ? V2 : V1;
+    const int64_t ldv = second ? ldv2 : ldv1;
+    const int w = second ? w2 : w1;
     const int c = int(idx % kPanel);
     const int x = int((idx / kPanel) % 256);
     const int64_t hs = idx / (int64_t(kPanel) * 256);
-    if (hs >= int64_t(halves) * k) return;
     const int sr = int(hs % k), h = int(hs / k);
     const uint32_t xv = uint32_t(x) << (8 * h);
     const uint32_t v = c < w ? ld_el(V, wide, sr * ldv + c) : 0u;
     const uint32_t prod = (xv >> e) == 0 ? F.exp[F.log[xv] + F.log[v]] : 0u;
-    st_el(T, wide, idx, prod);
+    st_el(second ? T2 : T1, wide, idx, prod);
 }
 
 // Applies the table of V (grease_build_kernel) to the rows of X (k columns):
@@ -413,13 +421,17 @@ __global__ __launch_bounds__(256) void grease_build_kernel(const void* V, int64_
 //     out[i][c] = (Cin ? Cin[i][c] : 0) + sum_{s < k} X[i][s] * V[s][c].
 // Cin and Cout have w columns (entries past them count as zero), orig takes
 // columns c < ow (zero beyond; uint16, pitch kPanel); either output may be
-// null.  Rows below x_lo are not written to Cout and copy Cin into orig.  Sixteen threads share a row, each
-// owning four columns; they read the row of X and the table rows that its
-// entries select (64 bytes of a table row per entry and half).
+// null.  Rows below x_lo are not written to Cout and copy Cin into orig.
+// With Pv set, rows pr0..pr0+k-1 take Pv - I instead (Pv: k x k, pitch k;
+// written to Cout only): in the one product that finishes a panel these
+// rows turn the pivot rows Y into Pv * Y = Y + (Pv - I) * Y.  Sixteen
+// threads share a row, each owning four columns; they read the row of X and
+// the table rows that its entries select (64 bytes of a table row per entry
+// and half).
 __global__ __launch_bounds__(256) void grease_apply_kernel(const void* X, int64_t ldx, int k, int64_t m, int64_t x_lo,
                                                            const void* T, int halves, int wide, const void* Cin,
                                                            int64_t ldcin, void* Cout, int64_t ldcout, int w,
-                                                           uint16_t* orig, int ow)
+                                                           uint16_t* orig, int ow, const void* Pv, int64_t pr0)
 {
     // The workgroup's sixteen rows of X go through LDS first (each thread
     // loads four entries), so that every thread then issues all its table
@@ -427,11 +439,19 @@ __global__ __launch_bounds__(256) void grease_apply_kernel(const void* X, int64_
     __shared__ uint32_t xl[16][kPanel];
     const int rl = threadIdx.x / 16, c4 = 4 * (threadIdx.x % 16);
     const int64_t i = int64_t(blockIdx.x) * 16 + rl;
-    const bool live = i < m && i >= x_lo;
+    const bool pivot = Pv && i >= pr0 && i < pr0 + k;
+    const bool live = i < m && i >= x_lo && !pivot;
 #pragma unroll
     for (int j = 0; j < 4; ++j) xl[rl][c4 + j] = live && c4 + j < k ? ld_el(X, wide, i * ldx + c4 + j) : 0u;
     __syncthreads();
     if (i >= m) return;
+    if (pivot) {
+        const int t = int(i - pr0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (c4 + j < w) st_el(Cout, wide, i * ldcout + c4 + j, ld_el(Pv, wide, t * k + c4 + j) ^ (c4 + j == t ? 1u : 0u));
+        return;
+    }
     uint32_t acc[4] = {0u, 0u, 0u, 0u};
     if (Cin)
 #pragma unroll
@@ -485,17 +505,6 @@ __global__ __launch_bounds__(256) void grease_apply_kernel(const void* X, int64_
     if (orig)
 #pragma unroll
         for (int j = 0; j < 4; ++j) orig[i * kPanel + c4 + j] = c4 + j < ow ? uint16_t(acc[j]) : 0;
-}
-
-// Rows r..r+k-1 of H (pitch ldh) = V - I for a k x k block V (pitch k): in
-// the one product that finishes a panel, these rows turn the pivot rows Y
-// into V * Y = Y + (V - I) * Y.
-__global__ void pivot_rows_kernel(const void* V, int k, void* H, int64_t ldh, int64_t r, int wide)
-{
-    const int idx = int(blockIdx.x) * 256 + threadIdx.x;
-    if (idx >= k * k) return;
-    const int t = idx / k, sc = idx % k;
-    st_el(H, wide, (r + t) * ldh + sc, ld_el(V, wide, idx) ^ (t == sc ? 1u : 0u));
 }
 
 dim3 rows_grid(int64_t rows, int64_t cols)
@@ -599,7 +608,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                   b_state = al(sizeof(PanelState)), b_perm = al((m + 2 * kPanel) * 4),
                   b_w = al(int64_t(kPanel) * kPanel * esz), b_g = al(m * kPanel * esz),
                   b_mv = al(2 * kPanel * n * esz), b_lu = ple ? 6 * b_w : 0,
-                  b_tab = al(2 * int64_t(kPanel) * 256 * kPanel * esz), b_h = al(m * kPanel * esz);
+                  b_tab = al(4 * int64_t(kPanel) * 256 * kPanel * esz), b_h = al(m * kPanel * esz);
     int rc = ensure_aux(b_orig + 2 * b_cand + b_state + b_perm + b_w + b_g + b_mv + b_lu + b_tab + b_h, s);
     if (rc) return rc;
     uint8_t* base = static_cast<uint8_t*>(aux);
@@ -705,17 +714,22 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         if (hipGetLastError() != hipSuccess || hipEventRecord(sel_done, s2) != hipSuccess) return GF2E_EDEVICE;
         return GF2E_OK;
     };
-    // out = (Cin) + X * V for a k x w block V (k, w <= kPanel) on s, by a
-    // table of V's multiples (grease_build_kernel, grease_apply_kernel); X,
-    // Cin and Cout indexed by absolute row, rows below x_lo left alone.
-    auto grease = [&](const void* V, int64_t ldv, int k, int w, const void* X, int64_t ldx, int64_t x_lo,
-                      const void* Cin, int64_t ldcin, void* Cout, int64_t ldcout, uint16_t* o, int ow) -> int {
-        if (k <= 0) return GF2E_OK;
-        const int64_t entries = int64_t(halves) * k * 256 * kPanel;
-        hipLaunchKernelGGL(grease_build_kernel, dim3(unsigned(ceil_div(entries, 256))), dim3(256), 0, s, V, ldv, k,
-                           w, halves, F, e, wide, static_cast<void*>(Tab));
+    // Products with a short inner dimension k <= kPanel on s by tables of
+    // multiples: build() writes the tables of V1 (to Tab) and of V2 (to Tab2,
+    // when set) in one launch; apply() forms out = (Cin) + X * V from a table
+    // (X, Cin and Cout indexed by absolute row, rows below x_lo left alone;
+    // with Pv set, rows r..r+k-1 of Cout take Pv - I).
+    uint8_t* Tab2 = Tab + b_tab / 2;
+    auto build = [&](int k, const void* V1, int64_t ldv1, int w1, const void* V2, int64_t ldv2, int w2) -> int {
+        const int64_t entries = int64_t(halves) * k * 256 * kPanel * (V2 ? 2 : 1);
+        hipLaunchKernelGGL(grease_build_kernel, dim3(unsigned(ceil_div(entries, 256))), dim3(256), 0, s, V1, ldv1, w1,
+                           static_cast<void*>(Tab), V2, ldv2, w2, static_cast<void*>(Tab2), k, halves, F, e, wide);
+        return hipGetLastError() == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
+    };
+    auto apply = [&](const uint8_t* T, int k, const void* X, int64_t ldx, int64_t x_lo, const void* Cin, int64_t ldcin,
+                     void* Cout, int64_t ldcout, int w, uint16_t* o, int ow, const void* Pv) -> int {
         hipLaunchKernelGGL(grease_apply_kernel, dim3(unsigned(ceil_div(m, 16))), dim3(256), 0, s, X, ldx, k, m, x_lo,
-                           static_cast<const void*>(Tab), halves, wide, Cin, ldcin, Cout, ldcout, w, o, ow);
+                           static_cast<const void*>(T), halves, wide, Cin, ldcin, Cout, ldcout, w, o, ow, Pv, r);
         return hipGetLastError() == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
     };
     if (n > 0 && (rc = start_search(0, 0, true))) return rc;
@@ -816,15 +830,17 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         // V - I, so that the pivot rows become V * Y, and the other rows add
         // their multiples of V * Y.  Before it, the next panel's copy is
         // computed from the same H and Y by a table (orig = A + H * Y on the
-        // next panel's columns) and the next pivot search starts on the side
-        // stream (its rows begin at rn).
+        // next panel's columns, from Tab2, which the caller built from the
+        // next panel's columns of Y) and the next pivot search starts on the
+        // side stream (its rows begin at rn).
+        uint8_t* Y = Ad + (r * lda + c0) * esz;
+        const int bcn = next ? int(std::min<int64_t>(kPanel, n - c0 - kPanel)) : 0;
+        const void* Ynext = next ? static_cast<const void*>(Y + kPanel * esz) : nullptr;
         auto finish = [&](int64_t lo, int64_t rn) -> int {
-            uint8_t* Y = Ad + (r * lda + c0) * esz;
             int rc2;
             if (next) {
-                const int bcn = int(std::min<int64_t>(kPanel, n - c0 - kPanel));
-                if ((rc2 = grease(Y + kPanel * esz, lda, rp, bcn, H, rp, lo, Ad + (c0 + kPanel) * esz, lda, nullptr, 0,
-                                  orig, bcn)))
+                if ((rc2 = apply(Tab2, rp, H, rp, lo, Ad + (c0 + kPanel) * esz, lda, nullptr, 0, bcn, orig, bcn,
+                                 nullptr)))
                     return rc2;
                 if ((rc2 = start_search(c0 + kPanel, rn, false))) return rc2;
             }
@@ -832,11 +848,6 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             const gf2e_mat Ym{Y, rp, nc, lda};
             gf2e_mat Cm{Ad + (lo * lda + c0) * esz, m - lo, nc, lda};
             return mul(e, f, &Hm, &Ym, &Cm, s, true);
-        };
-        auto pivot_rows = [&](const void* V) -> int {
-            hipLaunchKernelGGL(pivot_rows_kernel, dim3(unsigned(ceil_div(rp * rp, 256))), dim3(256), 0, s, V, rp,
-                               static_cast<void*>(H), int64_t(rp), r, wide);
-            return hipGetLastError() == hipSuccess ? GF2E_OK : GF2E_EDEVICE;
         };
 
         if (ple) {
@@ -854,14 +865,15 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             if (hipMemcpy2DAsync(Ld + (r * ldl + r) * esz, size_t(ldl * esz), Lk, size_t(rp * esz),
                                  size_t(rp * esz), size_t(rp), hipMemcpyDeviceToDevice, s) != hipSuccess)
                 return GF2E_EDEVICE;
-            const int64_t below = m - r - rp;
-            if (below > 0) {
-                if ((rc = grease(Ukinv, rp, rp, rp, G, rp, r + rp, nullptr, 0, Ld + r * esz, ldl, nullptr, 0)))
-                    return rc;
-                if ((rc = grease(Lkinv, rp, rp, rp, Ld + r * esz, ldl, r + rp, nullptr, 0, H, rp, nullptr, 0)))
-                    return rc;
-            }
-            if ((rc = pivot_rows(Lkinv)) || (rc = finish(r, r + rp))) return rc;
+            // L below (rows r + rp on) from Uk^{-1}'s table, then H: Lk^{-1}'s
+            // table on L below, Lk^{-1} - I on the pivot rows.  (The last
+            // panel has no rows below: only the pivot rows of H are written.)
+            if ((rc = build(rp, Ukinv, rp, rp, Ynext, lda, bcn)) ||
+                (rc = apply(Tab, rp, G, rp, r + rp, nullptr, 0, Ld + r * esz, ldl, rp, nullptr, 0, nullptr)) ||
+                (rc = build(rp, Lkinv, rp, rp, nullptr, 0, 0)) ||
+                (rc = apply(Tab, rp, Ld + r * esz, ldl, r + rp, nullptr, 0, H, rp, rp, nullptr, 0, Lkinv)) ||
+                (rc = finish(r, r + rp)))
+                return rc;
             r += rp;
             continue;
         }
@@ -869,8 +881,8 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         // the pivot rows become X1 = W * (pivot rows), every other row adds
         // G * X1 (G is zero on the pivot rows).
         const int64_t lo = full ? 0 : r;
-        if ((rc = grease(W, rp, rp, rp, G, rp, lo, nullptr, 0, H, rp, nullptr, 0)) || (rc = pivot_rows(W)) ||
-            (rc = finish(lo, r + rp)))
+        if ((rc = build(rp, W, rp, rp, Ynext, lda, bcn)) ||
+            (rc = apply(Tab, rp, G, rp, lo, nullptr, 0, H, rp, rp, nullptr, 0, W)) || (rc = finish(lo, r + rp)))
             return rc;
         r += rp;
     }
