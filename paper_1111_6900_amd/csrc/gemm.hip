@@ -502,6 +502,13 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
             for (int i = 0; i < FM; ++i) a[i] = sa.get(buf, c, wr * WM + 16 * i + l16);
 #pragma unroll
             for (int j = 0; j < FN; ++j) b[j] = sb.get(buf, c, wc * WN + 16 * j + l16);
+            // The wave raises its issue priority for its block of MFMAs, so
+            // that the SIMD's arbiter keeps the matrix core fed from it while
+            // the other waves' LDS reads and stores fill the gaps; the
+            // scheduling barriers keep the block whole.
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -510,6 +517,9 @@ __device__ __attribute__((always_inline)) inline void fp4_tile(
                     // operands make the compiler emit the unscaled form.
                     acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 4, 4, 0,
                                                                                 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
 
