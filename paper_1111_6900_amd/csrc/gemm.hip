@@ -559,6 +559,111 @@ __device__ __attribute__((always_inline)) inline void xcd_tile(int tiles_m, int 
     tn = (xcd % kRegN) * rn + local % rn;
 }
 
+// The 128x128 tile with both sides packed, its operands moved from HBM into
+// LDS by the direct global-to-LDS load (16 bytes per lane: two rows of one
+// k-word, lane l's pair at 16 l bytes from the wave's LDS address), four
+// LDS buffers deep: stages st + 1 .. st + 3 are in flight while stage st
+// computes, with no staging registers and no LDS store instructions.  LDS
+// holds each side as [buffer][k-word][row] 64-bit words, rows padded by 16
+// so that the two k-words a read touches fall on different halves of the
+// 64 banks (37 KiB per workgroup, four workgroups per compute unit).
+template <int BM, int BN, int WM, int WN>
+__device__ __attribute__((always_inline)) inline void fp4_tile_dma(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
+    int64_t Mp, int64_t Np, int64_t K64p, int tile_m, int tile_n)
+{
+    using TL = MfmaTile<BM, BN, WM, WN>;
+    constexpr int FM = TL::FM, FN = TL::FN;
+    constexpr int KW = 4, NB = 4, PR = 16;
+    static_assert(BM == 128 && BN == 128 && TL::kThreads == 256, "one wave instruction moves the 128 rows of one k-word");
+    static_assert(NB == 4, "the waits below count two loads per wave and stage, at most NB - 2 = 2 stages ahead");
+    typedef __attribute__((address_space(3))) void lds_void;
+    __shared__ uint64_t la[NB][KW][BM + PR];
+    __shared__ uint64_t lb[NB][KW][BN + PR];
+    const uint64_t* Ap = Apl + int64_t(tile_m) * BM;
+    const uint64_t* Bp = Bpl + int64_t(tile_n) * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
+    const int nstages = int(K64p / KW);
+    // Wave w moves k-words 2 (w & 1) and 2 (w & 1) + 1 of side w >> 1.
+    const bool aside = __builtin_amdgcn_readfirstlane(wave) < 2;
+    const int kw0 = 2 * (__builtin_amdgcn_readfirstlane(wave) & 1);
+    auto issue = [&](int st, int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kw = kw0 + q;
+            const int64_t word = int64_t(st) * KW + kw;
+            const uint64_t* src = aside ? Ap + word * Mp : Bp + word * Np;
+            lds_void* dst = aside ? (lds_void*)&la[buf][kw][0] : (lds_void*)&lb[buf][kw][0];
+            __builtin_amdgcn_global_load_lds((const void*)(src + 2 * lane), dst, 16, 0, 0);
+        }
+    };
+
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
+
+    const int g = lane >> 4, l16 = lane & 15;
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            const int kw = 2 * kb + (g >> 1), half = g & 1;
+            v8i a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = fp4_operand(expand_fp4<false>(
+                    reinterpret_cast<const uint32_t*>(&la[buf][kw][wr * WM + 16 * i + l16])[half]));
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = fp4_operand(expand_fp4<true>(
+                    reinterpret_cast<const uint32_t*>(&lb[buf][kw][wc * WN + 16 * j + l16])[half]));
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 4, 4, 0, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q)
+        if (q < nstages) issue(q, q);
+    for (int st = 0; st < nstages; ++st) {
+        // This wave's loads of stage st are done once only the two of each
+        // later stage in flight remain (vmcnt counts this wave's loads, which
+        // complete in order); the barrier then publishes every wave's.  (A
+        // plain __syncthreads would wait for every load in flight.)
+        {
+            const int ahead = min(NB - 2, nstages - 1 - st);
+            if (ahead >= 2)
+                __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4), lgkmcnt and expcnt not waited for
+            else if (ahead == 1)
+                __builtin_amdgcn_s_waitcnt(0x0F72);  // vmcnt(2)
+            else
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        }
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // Buffer (st + 3) % 4 was last read by stage st - 1, which every
+        // wave finished before the barrier.
+        if (st + NB - 1 < nstages) issue(st + NB - 1, (st + NB - 1) % NB);
+        compute(st % NB);
+        products_before_stores(acc);
+    }
+
+    fp4_store_parity<BM, BN, WM, WN>(acc, Ps, Np, tile_m, tile_n, wr, wc, lane);
+}
+
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB>
 __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__((amdgpu_waves_per_eu(2))) void gemm_fp4_kernel(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ P,
@@ -567,8 +672,12 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
     const int64_t s = blockIdx.z;
     int tm, tn;
     xcd_tile(tiles_m, tiles_n, tm, tn);
-    fp4_tile<BM, BN, WM, WN, KB, FA, FB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
-                                 Np, K64p, tm, tn);
+    if constexpr (BM == 128 && BN == 128 && KB == 2 && FA == kPacked && FB == kPacked)
+        fp4_tile_dma<BM, BN, WM, WN>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp, Np, K64p,
+                                     tm, tn);
+    else
+        fp4_tile<BM, BN, WM, WN, KB, FA, FB>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp,
+                                             Np, K64p, tm, tn);
 }
 
 // Planes s0..s1-1 of one tile as one pipeline of stages (KB 128-bit

@@ -85,8 +85,12 @@ def test_slice_figure1(g, ctx, golden_dir):
 
 @pytest.mark.parametrize("kind", list(range(9)))
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 200, 33), (64, 128, 64), (130, 384, 250),
-                                   (256, 64, 512), (513, 1000, 300)])
+                                   (256, 64, 512), (513, 1000, 300), (40, 700, 90), (70, 1500, 140),
+                                   (129, 2304, 200)])
 def test_plane_products(g, ctx, kind, shape):
+    """k from 1 to 9 stages of 256 bits: the kernels that keep several
+    stages in flight (up to three) also run with fewer stages than that and
+    with LDS buffers reused."""
     m, k, n = shape
     print(f"products kind={kind} shape={shape}", flush=True)
     t = 5
