@@ -559,6 +559,37 @@ __device__ __attribute__((always_inline)) inline void xcd_tile(int tiles_m, int 
     tn = (xcd % kRegN) * rn + local % rn;
 }
 
+// Waits until at most N of this wave's vector memory operations are in
+// flight (loads complete in the order they were issued); expcnt and lgkmcnt
+// are not waited for.
+template <int N>
+__device__ __attribute__((always_inline)) inline void wait_vmcnt()
+{
+    static_assert(N >= 0 && N <= 15, "the immediate's low vmcnt field");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+// The wait of a pipeline stage whose loads (PER per wave and stage) must be
+// done while those of the `ahead` (at most 2) later stages stay in flight.
+template <int PER>
+__device__ __attribute__((always_inline)) inline void wait_stage_loads(int ahead)
+{
+    if (ahead >= 2)
+        wait_vmcnt<2 * PER>();
+    else if (ahead == 1)
+        wait_vmcnt<PER>();
+    else
+        wait_vmcnt<0>();
+}
+// Workgroup barrier without the memory fence of __syncthreads, whose fence
+// would wait for every load in flight; the empty asm statements keep the
+// compiler from moving memory accesses across it.
+__device__ __attribute__((always_inline)) inline void stage_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // The 128x128 tile with both sides packed, its operands moved from HBM into
 // LDS by the direct global-to-LDS load (16 bytes per lane: two rows of one
 // k-word, lane l's pair at 16 l bytes from the wave's LDS address), four
@@ -576,7 +607,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
     constexpr int FM = TL::FM, FN = TL::FN;
     constexpr int KW = 4, NB = 4, PR = 16;
     static_assert(BM == 128 && BN == 128 && TL::kThreads == 256, "one wave instruction moves the 128 rows of one k-word");
-    static_assert(NB == 4, "the waits below count two loads per wave and stage, at most NB - 2 = 2 stages ahead");
+    static_assert(NB == 4, "the waits count at most NB - 2 = 2 stages ahead");
     typedef __attribute__((address_space(3))) void lds_void;
     __shared__ uint64_t la[NB][KW][BM + PR];
     __shared__ uint64_t lb[NB][KW][BN + PR];
@@ -639,21 +670,10 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
         if (q < nstages) issue(q, q);
     for (int st = 0; st < nstages; ++st) {
         // This wave's loads of stage st are done once only the two of each
-        // later stage in flight remain (vmcnt counts this wave's loads, which
-        // complete in order); the barrier then publishes every wave's.  (A
-        // plain __syncthreads would wait for every load in flight.)
-        {
-            const int ahead = min(NB - 2, nstages - 1 - st);
-            if (ahead >= 2)
-                __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4), lgkmcnt and expcnt not waited for
-            else if (ahead == 1)
-                __builtin_amdgcn_s_waitcnt(0x0F72);  // vmcnt(2)
-            else
-                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-        }
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
+        // later stage in flight remain; the barrier then publishes every
+        // wave's.
+        wait_stage_loads<2>(min(NB - 2, nstages - 1 - st));
+        stage_barrier();
         // Buffer (st + 3) % 4 was last read by stage st - 1, which every
         // wave finished before the barrier.
         if (st + NB - 1 < nstages) issue(st + NB - 1, (st + NB - 1) % NB);
@@ -791,13 +811,118 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile_at(
     }
 }
 
+// Planes s0..s1-1 of one 128x128 tile as one pipeline of stages of 2 KB
+// k-words, as fp4_planes_tile_at computes them, with the operands moved by
+// the direct global-to-LDS load (see fp4_tile_dma): four LDS buffers, the
+// next three stages in flight across plane boundaries, KB loads per wave and
+// stage.  The B side is read in the grouped column order; its rows sit in
+// LDS in pairs permuted by slot = column ^ (bit 5 of column) << 2 (lane l of
+// a load takes the pair that belongs at slots 2l, 2l + 1), and its pitch is
+// padded by 8 rows, so that the 32 words one read touches in each k-word
+// cover half of the 64 banks and the two k-words the other half.  The A side
+// is read in row order, pitch padded by 16 rows.
+template <int KB, class PlaneDone>
+__device__ __attribute__((always_inline)) inline void fp4_planes_tile_dma(
+    const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int s0, int s1, PlaneAddr ad, int64_t K64p,
+    int tile_m, int tile_n, PlaneDone&& plane_done)
+{
+    using TL = MfmaTile<128, 128, 64, 64>;
+    constexpr int FM = TL::FM, FN = TL::FN, WM = 64, WN = 64;
+    constexpr int KW = 2 * KB, NB = 4, PA = 16, PB = 8;
+    static_assert(KB == 1 || KB == 2, "stages of one or two 128-bit k-blocks");
+    typedef __attribute__((address_space(3))) void lds_void;
+    __shared__ uint64_t la[NB][KW][128 + PA];
+    __shared__ uint64_t lb[NB][KW][128 + PB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
+    const int nst = int(K64p / KW);  // stages per plane
+    const int G = (s1 - s0) * nst;   // stages of all planes
+    // Wave w moves k-words KB (w & 1) .. KB (w & 1) + KB - 1 of side w >> 1.
+    const int uw = __builtin_amdgcn_readfirstlane(wave);
+    const bool aside = uw < 2;
+    const int kw0 = KB * (uw & 1);
+    const int bcol = (2 * lane) ^ (((lane >> 4) & 1) << 2);  // B column pair loaded into slots 2 lane, + 1
+    auto issue = [&](int g, int buf) {
+        const int64_t s = s0 + g / nst, st = g % nst;
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            const int kw = kw0 + q;
+            const int64_t word = st * KW + kw;
+            const uint64_t* src = aside ? Apl + s * ad.a_pstride + int64_t(tile_m) * 128 + word * ad.lda + 2 * lane
+                                        : Bpl + s * ad.b_pstride + int64_t(tile_n) * 128 + word * ad.ldb + bcol;
+            lds_void* dst = aside ? (lds_void*)&la[buf][kw][0] : (lds_void*)&lb[buf][kw][0];
+            __builtin_amdgcn_global_load_lds((const void*)src, dst, 16, 0, 0);
+        }
+    };
+
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
+
+    const int g4 = lane >> 4, l16 = lane & 15;
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const int kw = 2 * kb + (g4 >> 1), half = g4 & 1;
+            v8i a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = fp4_operand(expand_fp4<false>(
+                    reinterpret_cast<const uint32_t*>(&la[buf][kw][wr * WM + 16 * i + l16])[half]));
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {  // grouped column order (fp4_parity_words_grouped)
+                const int col = wc * WN + 64 * (j >> 2) + 16 * (l16 >> 2) + 4 * (j & 3) + (l16 & 3);
+                const int slot = col ^ (((col >> 5) & 1) << 2);
+                b[j] = fp4_operand(
+                    expand_fp4<true>(reinterpret_cast<const uint32_t*>(&lb[buf][kw][slot])[half]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(b[j], a[i], acc[i][j], 4, 4, 0, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_setprio(0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+#pragma unroll
+    for (int q = 0; q < NB - 1; ++q)
+        if (q < G) issue(q, q);
+    for (int g = 0; g < G; ++g) {
+        wait_stage_loads<KB>(min(NB - 2, G - 1 - g));
+        stage_barrier();
+        // Buffer (g + 3) % 4 was last read at stage g - 1.
+        if (g + NB - 1 < G) issue(g + NB - 1, (g + NB - 1) % NB);
+        compute(g % NB);
+        products_before_stores(acc);
+        if ((g + 1) % nst == 0) {  // last stage of plane s0 + g / nst
+            plane_done(s0 + g / nst, acc, wr, wc, lane);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
+        }
+    }
+}
+
 template <int BM, int BN, int WM, int WN, int KB, int FA, int FB, class PlaneDone>
 __device__ __attribute__((always_inline)) inline void fp4_planes_tile(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int s0, int s1, int64_t Mp, int64_t Np,
     int64_t K64p, int tile_m, int tile_n, PlaneDone&& plane_done)
 {
-    fp4_planes_tile_at<BM, BN, WM, WN, KB, FA, FB>(Apl, Bpl, s0, s1, PlaneAddr{K64p * Mp, K64p * Np, Mp, Np}, K64p,
-                                                   tile_m, tile_n, plane_done);
+    const PlaneAddr ad{K64p * Mp, K64p * Np, Mp, Np};
+    if constexpr (BM == 128 && BN == 128 && WM == 64 && WN == 64 && FA == kPacked && FB == kPacked)
+        fp4_planes_tile_dma<KB>(Apl, Bpl, s0, s1, ad, K64p, tile_m, tile_n, plane_done);
+    else
+        fp4_planes_tile_at<BM, BN, WM, WN, KB, FA, FB>(Apl, Bpl, s0, s1, ad, K64p, tile_m, tile_n, plane_done);
 }
 
 template <int BM, int BN, int WM, int WN, int FA, int FB>
@@ -875,7 +1000,9 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
         const uint32_t* __restrict__ om = P.omask;
 #pragma unroll
         for (int q = 0; q < kFusedMaxE; ++q) res[q][tid] = 0;  // this thread's slots only
-        fp4_planes_tile<BM, BN, WM, WN, 2, FA, FB>(
+        // Stages of one 128-bit k-block: four LDS buffers of them beside the
+        // result slots keep four workgroups on a compute unit.
+        fp4_planes_tile<BM, BN, WM, WN, 1, FA, FB>(
             P.Apl, P.Bpl, 0, P.T, P.Mp, P.Np, P.K64p, w.tile_m, w.tile_n,
             [&](int s, const auto& acc, int wr, int wc, int lane) {
                 uint64_t mine = 0;
@@ -919,8 +1046,7 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
 // lane holds plane c of its word of the result (kept in LDS); it then clings
 // the E planes into C (C = A * B, or C += A * B with acc).  No product
 // planes are written and no combining pass runs.  For E <= kFusedMaxE; Kw
-// (words of k) a multiple of 2 KB.
-template <int KB>
+// (words of k) even.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_fp4_fused_alpha(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, int E, int64_t Mp, int64_t Np, int64_t Kw,
     int64_t m, int64_t n, void* __restrict__ C, int64_t ldc, int acc)
@@ -929,7 +1055,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     static_assert(kFusedMaxE == 10, "the clinging switch below covers e = 2..10");
     __shared__ uint64_t res[kFusedMaxE][TL::kThreads];
     const int tid = threadIdx.x, tm = blockIdx.y, tn = blockIdx.x;
-    fp4_planes_tile_at<128, 128, 64, 64, KB, kPacked, kPacked>(
+    fp4_planes_tile_dma<1>(
         Apl, Bpl, 0, E, PlaneAddr{0, Np, Mp, int64_t(E) * Np}, Kw, tm, tn,
         [&](int c, const auto& a, int wr, int wc, int lane) {
             uint64_t mine = 0;
@@ -1181,12 +1307,7 @@ hipError_t launch_fused_alpha(int e, const uint64_t* Apl, const uint64_t* Bpl, i
         return hipErrorInvalidValue;
     if (m == 0 || n == 0) return hipSuccess;
     const dim3 grid{unsigned(tn), unsigned(tm)}, block{unsigned(MfmaTile<128, 128, 64, 64>::kThreads)};
-    if (Kw % 4 == 0)
-        hipLaunchKernelGGL(gemm_fp4_fused_alpha<2>, grid, block, 0, s, Apl, Bpl, e, Mp, Np, Kw, m, n, C, ldc,
-                           acc ? 1 : 0);
-    else
-        hipLaunchKernelGGL(gemm_fp4_fused_alpha<1>, grid, block, 0, s, Apl, Bpl, e, Mp, Np, Kw, m, n, C, ldc,
-                           acc ? 1 : 0);
+    hipLaunchKernelGGL(gemm_fp4_fused_alpha, grid, block, 0, s, Apl, Bpl, e, Mp, Np, Kw, m, n, C, ldc, acc ? 1 : 0);
     return hipGetLastError();
 }
 
