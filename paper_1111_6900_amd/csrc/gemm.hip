@@ -580,6 +580,19 @@ __device__ __attribute__((always_inline)) inline void wait_stage_loads(int ahead
     else
         wait_vmcnt<0>();
 }
+typedef __attribute__((address_space(3))) void lds_void;
+// The LDS address of p as the destination of a direct global-to-LDS load,
+// passed through an empty asm statement: the compiler then does not know
+// which LDS array the load writes, and does not make every LDS read wait
+// for all such loads in flight (the kernels order them with their own
+// vmcnt waits and barriers).
+__device__ __attribute__((always_inline)) inline lds_void* lds_dst(const void* p)
+{
+    uint32_t a = uint32_t(uintptr_t((const lds_void*)p));
+    asm("" : "+s"(a));
+    return (lds_void*)uintptr_t(a);
+}
+
 // Workgroup barrier without the memory fence of __syncthreads, whose fence
 // would wait for every load in flight; the empty asm statements keep the
 // compiler from moving memory accesses across it.
@@ -606,9 +619,13 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
     using TL = MfmaTile<BM, BN, WM, WN>;
     constexpr int FM = TL::FM, FN = TL::FN;
     constexpr int KW = 4, NB = 4, PR = 16;
-    static_assert(BM == 128 && BN == 128 && TL::kThreads == 256, "one wave instruction moves the 128 rows of one k-word");
+    // Loads per stage: one per k-word and 128 rows of a side, LA of A and LB
+    // of B per wave; wave w issues loads w, w + W, w + 2 W, ... of each side
+    // (load t moves k-word t % KW of rows 128 (t / KW) ..).
+    constexpr int W = TL::kWaves, LA = KW * BM / 128 / W, LB = KW * BN / 128 / W, PER = LA + LB;
+    static_assert(BM % 128 == 0 && BN % 128 == 0 && LA * W * 128 == KW * BM && LB * W * 128 == KW * BN,
+                  "whole wave loads of 128 rows of one k-word per side");
     static_assert(NB == 4, "the waits count at most NB - 2 = 2 stages ahead");
-    typedef __attribute__((address_space(3))) void lds_void;
     __shared__ uint64_t la[NB][KW][BM + PR];
     __shared__ uint64_t lb[NB][KW][BN + PR];
     const uint64_t* Ap = Apl + int64_t(tile_m) * BM;
@@ -616,17 +633,19 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::kWavesN, wc = wave % TL::kWavesN;
     const int nstages = int(K64p / KW);
-    // Wave w moves k-words 2 (w & 1) and 2 (w & 1) + 1 of side w >> 1.
-    const bool aside = __builtin_amdgcn_readfirstlane(wave) < 2;
-    const int kw0 = 2 * (__builtin_amdgcn_readfirstlane(wave) & 1);
+    const int uw = __builtin_amdgcn_readfirstlane(wave);
     auto issue = [&](int st, int buf) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int kw = kw0 + q;
-            const int64_t word = int64_t(st) * KW + kw;
-            const uint64_t* src = aside ? Ap + word * Mp : Bp + word * Np;
-            lds_void* dst = aside ? (lds_void*)&la[buf][kw][0] : (lds_void*)&lb[buf][kw][0];
-            __builtin_amdgcn_global_load_lds((const void*)(src + 2 * lane), dst, 16, 0, 0);
+        for (int q = 0; q < LA; ++q) {
+            const int t = uw + W * q, kw = t % KW, rb = 128 * (t / KW);
+            const uint64_t* src = Ap + (int64_t(st) * KW + kw) * Mp + rb + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void*)src, lds_dst(&la[buf][kw][rb]), 16, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int t = uw + W * q, kw = t % KW, rb = 128 * (t / KW);
+            const uint64_t* src = Bp + (int64_t(st) * KW + kw) * Np + rb + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void*)src, lds_dst(&lb[buf][kw][rb]), 16, 0, 0);
         }
     };
 
@@ -672,7 +691,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
         // This wave's loads of stage st are done once only the two of each
         // later stage in flight remain; the barrier then publishes every
         // wave's.
-        wait_stage_loads<2>(min(NB - 2, nstages - 1 - st));
+        wait_stage_loads<PER>(min(NB - 2, nstages - 1 - st));
         stage_barrier();
         // Buffer (st + 3) % 4 was last read by stage st - 1, which every
         // wave finished before the barrier.
@@ -692,7 +711,7 @@ __global__ __launch_bounds__((MfmaTile<BM, BN, WM, WN>::kThreads)) __attribute__
     const int64_t s = blockIdx.z;
     int tm, tn;
     xcd_tile(tiles_m, tiles_n, tm, tn);
-    if constexpr (BM == 128 && BN == 128 && KB == 2 && FA == kPacked && FB == kPacked)
+    if constexpr (BM == 128 && KB == 2 && FA == kPacked && FB == kPacked)
         fp4_tile_dma<BM, BN, WM, WN>(Apl + s * K64p * Mp, Bpl + s * K64p * Np, P + s * Mp * (Np / 64), Mp, Np, K64p,
                                      tm, tn);
     else
@@ -830,7 +849,6 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile_dma(
     constexpr int FM = TL::FM, FN = TL::FN, WM = 64, WN = 64;
     constexpr int KW = 2 * KB, NB = 4, PA = 16, PB = 8;
     static_assert(KB == 1 || KB == 2, "stages of one or two 128-bit k-blocks");
-    typedef __attribute__((address_space(3))) void lds_void;
     __shared__ uint64_t la[NB][KW][128 + PA];
     __shared__ uint64_t lb[NB][KW][128 + PB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -850,8 +868,8 @@ __device__ __attribute__((always_inline)) inline void fp4_planes_tile_dma(
             const int64_t word = st * KW + kw;
             const uint64_t* src = aside ? Apl + s * ad.a_pstride + int64_t(tile_m) * 128 + word * ad.lda + 2 * lane
                                         : Bpl + s * ad.b_pstride + int64_t(tile_n) * 128 + word * ad.ldb + bcol;
-            lds_void* dst = aside ? (lds_void*)&la[buf][kw][0] : (lds_void*)&lb[buf][kw][0];
-            __builtin_amdgcn_global_load_lds((const void*)src, dst, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)src, lds_dst(aside ? &la[buf][kw][0] : &lb[buf][kw][0]), 16,
+                                             0, 0);
         }
     };
 
