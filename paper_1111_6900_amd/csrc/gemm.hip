@@ -656,19 +656,29 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
         for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
 
     const int g = lane >> 4, l16 = lane & 15;
+    // The packed operands of a k-block; those of the stage's second k-block
+    // are read before the first one's MFMAs, so that their LDS latency
+    // passes under them.
+    auto read_raw = [&](int buf, int kb, uint32_t (&ra)[FM], uint32_t (&rb)[FN]) {
+        const int kw = 2 * kb + (g >> 1), half = g & 1;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            ra[i] = reinterpret_cast<const uint32_t*>(&la[buf][kw][wr * WM + 16 * i + l16])[half];
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            rb[j] = reinterpret_cast<const uint32_t*>(&lb[buf][kw][wc * WN + 16 * j + l16])[half];
+    };
     auto compute = [&](int buf) {
+        uint32_t ra[2][FM], rb[2][FN];
+        read_raw(buf, 0, ra[0], rb[0]);
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-            const int kw = 2 * kb + (g >> 1), half = g & 1;
             v8i a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
-                a[i] = fp4_operand(expand_fp4<false>(
-                    reinterpret_cast<const uint32_t*>(&la[buf][kw][wr * WM + 16 * i + l16])[half]));
+            for (int i = 0; i < FM; ++i) a[i] = fp4_operand(expand_fp4<false>(ra[kb][i]));
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                b[j] = fp4_operand(expand_fp4<true>(
-                    reinterpret_cast<const uint32_t*>(&lb[buf][kw][wc * WN + 16 * j + l16])[half]));
+            for (int j = 0; j < FN; ++j) b[j] = fp4_operand(expand_fp4<true>(rb[kb][j]));
+            if (kb == 0) read_raw(buf, 1, ra[1], rb[1]);
             __builtin_amdgcn_sched_barrier(0);
             __builtin_amdgcn_s_setprio(1);
             __builtin_amdgcn_sched_barrier(0);
