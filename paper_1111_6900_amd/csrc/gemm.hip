@@ -656,9 +656,10 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
         for (int j = 0; j < FN; ++j) acc[i][j] = v4f{kFp4Bias, kFp4Bias, kFp4Bias, kFp4Bias};
 
     const int g = lane >> 4, l16 = lane & 15;
-    // The packed operands of a k-block; those of the stage's second k-block
-    // are read before the first one's MFMAs, so that their LDS latency
-    // passes under them.
+    // The packed operands of a k-block.  Those of a stage's first k-block
+    // are read right after the stage's barrier, ahead of the next loads'
+    // issue, and those of its second k-block before the first one's MFMAs,
+    // so that their LDS latency passes under them.
     auto read_raw = [&](int buf, int kb, uint32_t (&ra)[FM], uint32_t (&rb)[FN]) {
         const int kw = 2 * kb + (g >> 1), half = g & 1;
 #pragma unroll
@@ -668,9 +669,8 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
         for (int j = 0; j < FN; ++j)
             rb[j] = reinterpret_cast<const uint32_t*>(&lb[buf][kw][wc * WN + 16 * j + l16])[half];
     };
+    uint32_t ra[2][FM], rb[2][FN];
     auto compute = [&](int buf) {
-        uint32_t ra[2][FM], rb[2][FN];
-        read_raw(buf, 0, ra[0], rb[0]);
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
             v8i a[FM], b[FN];
@@ -705,6 +705,7 @@ __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
         stage_barrier();
         // Buffer (st + 3) % 4 was last read by stage st - 1, which every
         // wave finished before the barrier.
+        read_raw(st % NB, 0, ra[0], rb[0]);
         if (st + NB - 1 < nstages) issue(st + NB - 1, (st + NB - 1) % NB);
         compute(st % NB);
         products_before_stores(acc);
