@@ -336,7 +336,8 @@ int gf2e_slice_a(gf2e_ctx* ctx, const gf2e_mat* A, int e, uint32_t f, uint64_t* 
 int gf2e_slice_b(gf2e_ctx* ctx, const gf2e_mat* B, int e, uint32_t f, uint64_t* planes, int64_t Np,
                  int64_t K64p, void* stream);
 /* P_s = Ahat_s * Bhat_s^T over GF(2) for s < t, one grouped launch of the
- * given kernel (GF2E_KERNEL_*, AUTO allowed). */
+ * given kernel (GF2E_KERNEL_*, AUTO allowed).  The three plane buffers must
+ * be 16-byte aligned (GF2E_EINVAL otherwise). */
 int gf2e_plane_products(gf2e_ctx* ctx, int kernel, int t, const uint64_t* a_planes,
                         const uint64_t* b_planes, uint64_t* p_planes, int64_t m, int64_t n,
                         int64_t Mp, int64_t Np, int64_t K64p, void* stream);

@@ -761,6 +761,9 @@ int gf2e_plane_products(gf2e_ctx* handle, int kernel, int t, const uint64_t* a_p
 {
     Ctx* c = reinterpret_cast<Ctx*>(handle);
     if (!c || !a_planes || !b_planes || !p_planes || t <= 0 || t > kMaxT) return GF2E_EINVAL;
+    // the fp4 kernels move operand rows in 16-byte pairs straight into LDS
+    auto aligned16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    if (!aligned16(a_planes) || !aligned16(b_planes) || !aligned16(p_planes)) return GF2E_EINVAL;
     if (m < 0 || n < 0 || Mp < m || Np < n || Mp % kRowAlign || Np % kRowAlign || K64p <= 0 ||
         K64p % 4)
         return GF2E_ESHAPE;

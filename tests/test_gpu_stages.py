@@ -111,6 +111,22 @@ def test_plane_products(g, ctx, kind, shape):
         assert (pm.unpack_rows(np.ascontiguousarray(got[s, :m]), n) == want[s]).all(), s
 
 
+def test_plane_products_rejects_unaligned_planes(g, ctx):
+    """The fp4 kernels load operand rows in 16-byte pairs: plane buffers off
+    a 16-byte boundary are refused before anything is launched."""
+    geo = g.plane_geometry(2, 0x7, 64, 256, 64)
+    t = 3
+    A = torch.zeros(t * geo.K64p * geo.Mp + 1, dtype=torch.int64, device="cuda")
+    B = torch.zeros(t * geo.K64p * geo.Np + 1, dtype=torch.int64, device="cuda")
+    P = torch.zeros(t * geo.Mp * (geo.Np // 64) + 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(g.GF2EError) as err:
+        ctx.plane_products(-1, t, A[1:], B[:-1], P[:-1], 64, 64, geo.Mp, geo.Np, geo.K64p)
+    assert err.value.code == g.EINVAL
+    ctx.plane_products(-1, t, A[:-1], B[:-1], P[:-1], 64, 64, geo.Mp, geo.Np, geo.K64p)
+    ctx.sync()
+    assert int(P.count_nonzero()) == 0
+
+
 @pytest.mark.parametrize("e,f", [(2, 0x7), (4, 0x13), (4, 0x1F), (5, 0x25), (8, 0x11D),
                                  (8, 0x11B), (9, 0x211), (10, 0x409)])
 @pytest.mark.parametrize("mn", [(1, 1), (5, 70), (64, 64), (130, 257)])
