@@ -126,6 +126,10 @@ constexpr int kSelRows = 256;   // rows per workgroup of the tournament
 constexpr int kSelParts = 4;    // lanes per row in the tournament levels
 constexpr int kFinalParts = 8;  // lanes per row in the final level (128 rows, 1024 threads)
 constexpr int kProbeRows = 128; // rows of the probe (2 kPanel: full rank unless the rows are special)
+// Fields from 2^6 elements on: 64 random rows of a 64-column panel are of
+// full rank with probability above 0.98, so the probe takes kPanel rows
+// with 16 lanes per row (4 columns per lane, shorter steps).
+constexpr int kShortProbeMinE = 6;
 
 template <int ROWS, int PARTS, bool LDS_TABS, bool FINAL>
 __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16_t* orig, int64_t r, int bc,
@@ -675,9 +679,8 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     // A pivot-search launch on the side stream for the panel of bc columns
     // whose rows start at r0; the final level (one workgroup) also writes the
     // panel state and W = K^{-1}.
-    auto launch_select = [&]<int ROWS, bool FIN>(int64_t r0, int bc, int64_t nb, int64_t ncand, const int* in,
-                                                 int* out) {
-        constexpr int PARTS = FIN ? kFinalParts : kSelParts;
+    auto launch_select = [&]<int ROWS, bool FIN, int PARTS = (FIN ? kFinalParts : kSelParts)>(
+                             int64_t r0, int bc, int64_t nb, int64_t ncand, const int* in, int* out) {
         const dim3 grid{unsigned(nb)}, block{unsigned(ROWS * PARTS)};
         if (lds_tabs)
             hipLaunchKernelGGL((panel_select_kernel<ROWS, PARTS, true, FIN>), grid, block, 0, s2, orig, r0, bc, in,
@@ -708,8 +711,12 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         if (copy)
             hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s2,
                                A->data, lda, m, c0n, bcn, wide, orig);
-        launch_select.template operator()<kProbeRows, true>(r0, bcn, 1, std::min<int64_t>(m - r0, kProbeRows),
-                                                            static_cast<const int*>(nullptr), cand[0]);
+        if (e >= kShortProbeMinE)
+            launch_select.template operator()<kPanel, true, 16>(r0, bcn, 1, std::min<int64_t>(m - r0, kPanel),
+                                                                static_cast<const int*>(nullptr), cand[0]);
+        else
+            launch_select.template operator()<kProbeRows, true>(r0, bcn, 1, std::min<int64_t>(m - r0, kProbeRows),
+                                                                static_cast<const int*>(nullptr), cand[0]);
         if (ple) launch_lu(c0n, r0);
         if (hipGetLastError() != hipSuccess || hipEventRecord(sel_done, s2) != hipSuccess) return GF2E_EDEVICE;
         return GF2E_OK;
@@ -740,7 +747,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         // whole tournament runs only when they lack a pivot in some column
         // and further rows exist.
         if (hipEventSynchronize(sel_done) != hipSuccess) return GF2E_EDEVICE;
-        const int64_t probe = std::min<int64_t>(mr, kProbeRows);
+        const int64_t probe = std::min<int64_t>(mr, e >= kShortProbeMinE ? kPanel : kProbeRows);
         if (hs.rp < bc && mr > probe) {
             // Tournament levels of kSelRows-row workgroups until at most
             // kProbeRows candidates remain, then the final level on those.
