@@ -657,19 +657,20 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
     // first brings the next panel's columns up to date (event ahead on s),
     // the search waits for that, and the rest of the update follows on s.
     hipStream_t s2 = side_stream();
-    hipEvent_t sel_done = get_event(), ahead = get_event();
-    if (!s2 || !sel_done || !ahead) return GF2E_EDEVICE;
+    // (PLE: the panel's LU factors follow the search on the side stream;
+    // the host waits only for the search, s for the factors, event lu_done.)
+    hipEvent_t sel_done = get_event(), ahead = get_event(), lu_done = get_event();
+    if (!s2 || !sel_done || !ahead || !lu_done) return GF2E_EDEVICE;
     struct EventBack {  // back to the pool on every return, the side stream drained
         Ctx* c;
         hipStream_t side;
-        hipEvent_t ev[2];
+        hipEvent_t ev[3];
         ~EventBack()
         {
             (void)hipStreamSynchronize(side);
-            c->event_pool.push_back(ev[0]);
-            c->event_pool.push_back(ev[1]);
+            for (hipEvent_t e : ev) c->event_pool.push_back(e);
         }
-    } event_back{this, s2, {sel_done, ahead}};
+    } event_back{this, s2, {sel_done, ahead, lu_done}};
     const PanelState& hs = *hsp;
     std::vector<char> is_piv;
     uint8_t* Ad = static_cast<uint8_t*>(A->data);
@@ -717,8 +718,11 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         else
             launch_select.template operator()<kProbeRows, true>(r0, bcn, 1, std::min<int64_t>(m - r0, kProbeRows),
                                                                 static_cast<const int*>(nullptr), cand[0]);
-        if (ple) launch_lu(c0n, r0);
         if (hipGetLastError() != hipSuccess || hipEventRecord(sel_done, s2) != hipSuccess) return GF2E_EDEVICE;
+        if (ple) {
+            launch_lu(c0n, r0);
+            if (hipGetLastError() != hipSuccess || hipEventRecord(lu_done, s2) != hipSuccess) return GF2E_EDEVICE;
+        }
         return GF2E_OK;
     };
     // Products with a short inner dimension k <= kPanel on s by tables of
@@ -761,10 +765,13 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
                 ncand = nb * kPanel;
             }
             launch_select.template operator()<kProbeRows, true>(r, bc, 1, ncand, in, cand[0]);
-            if (ple) launch_lu(c0, r);  // again, on the final pivots
-            if (hipGetLastError() != hipSuccess) return GF2E_EDEVICE;
-            if (hipStreamSynchronize(s2) != hipSuccess)
-                return GF2E_EDEVICE;
+            if (hipGetLastError() != hipSuccess || hipEventRecord(sel_done, s2) != hipSuccess) return GF2E_EDEVICE;
+            if (ple) {
+                launch_lu(c0, r);  // again, on the final pivots
+                if (hipGetLastError() != hipSuccess || hipEventRecord(lu_done, s2) != hipSuccess)
+                    return GF2E_EDEVICE;
+            }
+            if (hipEventSynchronize(sel_done) != hipSuccess) return GF2E_EDEVICE;
         }
         // (The host has seen the search complete, so the kernels enqueued on s
         // from here on read its panel state, W and panel copy.)
@@ -869,6 +876,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             // (L below) * Lk^{-1}] on rows r..m-1.
             uint8_t* Ld = static_cast<uint8_t*>(ple->L->data);
             const int64_t ldl = ple->L->ld;
+            if (hipStreamWaitEvent(s, lu_done, 0) != hipSuccess) return GF2E_EDEVICE;
             if (hipMemcpy2DAsync(Ld + (r * ldl + r) * esz, size_t(ldl * esz), Lk, size_t(rp * esz),
                                  size_t(rp * esz), size_t(rp), hipMemcpyDeviceToDevice, s) != hipSuccess)
                 return GF2E_EDEVICE;
