@@ -260,6 +260,111 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     }
 }
 
+// The final-level pivot search over F_4 (x^2 + x + 1) with every row in
+// one thread as two 64-bit planes (bit c of lo / hi: the x^0 / x^1
+// coefficient of column c), so that a step is a few word operations per
+// row instead of one table lookup per entry.  Same results as
+// panel_select_kernel<ROWS, PARTS, *, true>: the first row (in candidate
+// order) with a nonzero entry in column J becomes pivot J, column J is
+// eliminated from every other row (Gauss-Jordan), the combinations a (over
+// pivot columns) are carried along, and W = K^{-1}.  ROWS = 128 candidates,
+// one per thread.
+constexpr int kGf4Rows = 128;
+
+// m * (h x + l) over F_4 on bit-planes, m = m1 x + m0 as all-ones masks
+// (x^2 = x + 1): high plane m1 (h + l) + m0 h, low plane m1 h + m0 l.
+__device__ __attribute__((always_inline)) inline void gf4_axpy(uint64_t M1, uint64_t M0, uint64_t h, uint64_t l,
+                                                                uint64_t& dh, uint64_t& dl)
+{
+    dh ^= (M1 & (h ^ l)) ^ (M0 & h);
+    dl ^= (M1 & h) ^ (M0 & l);
+}
+// Product of two elements of F_4 (values 0..3).
+__device__ __attribute__((always_inline)) inline uint32_t gf4_mul(uint32_t a, uint32_t b)
+{
+    const uint32_t a1 = a >> 1, a0 = a & 1, b1 = b >> 1, b0 = b & 1;
+    return (((a1 & b1) ^ (a1 & b0) ^ (a0 & b1)) << 1) | ((a1 & b1) ^ (a0 & b0));
+}
+
+__global__ __launch_bounds__(kGf4Rows) void panel_select_gf4_kernel(const uint16_t* orig, int64_t r, int bc,
+                                                                    const int* in, int64_t ncand, PanelState* st,
+                                                                    PanelState* hst, void* W)
+{
+    __shared__ int wcand[kGf4Rows / 64];
+    __shared__ uint64_t prow[4];  // the pivot row: lo, hi, and its combination's lo, hi
+    __shared__ uint32_t pinv;     // inverse of the pivot entry
+    __shared__ int colpiv[kPanel];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = tid < ncand ? (in ? in[tid] : tid) : -1;
+    uint64_t lo = 0, hi = 0, alo = 0, ahi = 0;
+    if (row >= 0) {
+        const uint16_t* src = orig + (r + row) * kPanel;
+        for (int c = 0; c < bc; ++c) {
+            const uint64_t x = src[c];
+            lo |= (x & 1) << c;
+            hi |= ((x >> 1) & 1) << c;
+        }
+    }
+    if (tid < kPanel) colpiv[tid] = -1;
+    bool used = row < 0;
+    int npiv = 0, my_t = -1;
+    uint32_t my_inv = 0;
+    for (int J = 0; J < bc; ++J) {
+        // the first candidate with a nonzero entry in column J
+        const bool ok = !used && (((lo | hi) >> J) & 1);
+        const uint64_t bal = __ballot(ok);
+        if (lane == 0) wcand[wave] = bal ? wave * 64 + __ffsll(static_cast<long long>(bal)) - 1 : INT_MAX;
+        __syncthreads();
+        int p = INT_MAX;
+#pragma unroll
+        for (int w = 0; w < kGf4Rows / 64; ++w) p = min(p, wcand[w]);
+        if (p == INT_MAX) {  // no pivot in column J (uniform)
+            __syncthreads();  // wcand is read before the next step writes it
+            continue;
+        }
+        if (tid == p) {
+            alo |= uint64_t(1) << J;  // the pivot row's own coefficient
+            const uint32_t x = uint32_t(((hi >> J) & 1) << 1 | ((lo >> J) & 1));
+            my_inv = x == 1 ? 1u : x ^ 1u;  // 1/x: 1 -> 1, x -> x + 1, x + 1 -> x
+            prow[0] = lo;
+            prow[1] = hi;
+            prow[2] = alo;
+            prow[3] = ahi;
+            pinv = my_inv;
+            colpiv[J] = npiv;
+            st->rows[npiv] = row;
+            st->cols[npiv] = J;
+            hst->rows[npiv] = row;
+            hst->cols[npiv] = J;
+            used = true;
+            my_t = npiv;
+        }
+        ++npiv;  // uniform
+        __syncthreads();
+        if (tid != p) {
+            const uint32_t x = uint32_t(((hi >> J) & 1) << 1 | ((lo >> J) & 1));
+            const uint32_t mlt = gf4_mul(x, pinv);  // 0 for rows with nothing to eliminate
+            const uint64_t M1 = 0 - uint64_t(mlt >> 1), M0 = 0 - uint64_t(mlt & 1);
+            gf4_axpy(M1, M0, prow[1], prow[0], hi, lo);
+            gf4_axpy(M1, M0, prow[3], prow[2], ahi, alo);
+        }
+        __syncthreads();  // prow, pinv and wcand are read before the next step writes them
+    }
+    if (tid == 0) {
+        st->rp = npiv;
+        hst->rp = npiv;
+    }
+    // W[t][s] = coefficient of pivot row s (at its column) in pivot row t, over t's pivot
+    if (my_t >= 0)
+        for (int c = 0; c < bc; ++c) {
+            const int s2 = colpiv[c];
+            if (s2 >= 0) {
+                const uint32_t a = uint32_t(((ahi >> c) & 1) << 1 | ((alo >> c) & 1));
+                st_el(W, 0, int64_t(my_t) * npiv + s2, gf4_mul(a, my_inv));
+            }
+        }
+}
+
 // G[i][t] = original entry of (new) row i at pivot column t, for all rows:
 // rows i < r are unmoved, row r + k is old row r + perm[k] for k < plen and
 // unmoved beyond, and the pivot rows r..r+rp-1 get zeros (so that one
@@ -712,7 +817,11 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
         if (copy)
             hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s2,
                                A->data, lda, m, c0n, bcn, wide, orig);
-        if (e >= kShortProbeMinE)
+        if (e == 2)
+            hipLaunchKernelGGL(panel_select_gf4_kernel, dim3(1), dim3(kGf4Rows), 0, s2, orig, r0, bcn,
+                               static_cast<const int*>(nullptr), std::min<int64_t>(m - r0, kGf4Rows), st, hst_dev,
+                               static_cast<void*>(W));
+        else if (e >= kShortProbeMinE)
             launch_select.template operator()<kPanel, true, 16>(r0, bcn, 1, std::min<int64_t>(m - r0, kPanel),
                                                                 static_cast<const int*>(nullptr), cand[0]);
         else
