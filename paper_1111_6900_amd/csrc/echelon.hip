@@ -145,6 +145,10 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     __shared__ int plog[kPanel];
     __shared__ int alog[FINAL ? kPanel : 1];    // the pivot row's coefficients (logs)
     __shared__ int colpiv[FINAL ? kPanel : 1];  // pivot index of each panel column, -1 if none
+    // Row and column of each pivot, written out after the last step: stores
+    // to the panel state (host memory for the final level) inside the steps
+    // would make every later barrier wait for them.
+    __shared__ int prow_of[kPanel], pcol_of[kPanel];
     __shared__ int lead;
     const int tid = threadIdx.x, rl = tid / PARTS, part = tid % PARTS, lane = tid & 63;
     const int q = int(F.q);
@@ -207,14 +211,8 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
         __syncthreads();
         if (rl == p) {
             if (part == 0) {
-                if constexpr (FINAL) {
-                    st->rows[npiv] = row;
-                    st->cols[npiv] = J;
-                    hst->rows[npiv] = row;
-                    hst->cols[npiv] = J;
-                } else {
-                    out[int64_t(blockIdx.x) * kPanel + npiv] = row;
-                }
+                prow_of[npiv] = row;
+                pcol_of[npiv] = J;
             }
             used = true;
             my_t = npiv;
@@ -241,7 +239,14 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     [&]<int... J>(std::integer_sequence<int, J...>) __attribute__((always_inline)) {
         (step.template operator()<J>(), ...);
     }(std::make_integer_sequence<int, kPanel>{});
+    __syncthreads();  // prow_of and pcol_of are complete
     if constexpr (FINAL) {
+        if (tid < npiv) {
+            st->rows[tid] = prow_of[tid];
+            st->cols[tid] = pcol_of[tid];
+            hst->rows[tid] = prow_of[tid];
+            hst->cols[tid] = pcol_of[tid];
+        }
         if (tid == 0) {
             st->rp = npiv;
             hst->rp = npiv;
@@ -255,8 +260,7 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
             }
         }
     } else {
-        if (tid == 0)
-            for (int t = npiv; t < kPanel; ++t) out[int64_t(blockIdx.x) * kPanel + t] = -1;
+        if (tid < kPanel) out[int64_t(blockIdx.x) * kPanel + tid] = tid < npiv ? prow_of[tid] : -1;
     }
 }
 
@@ -294,6 +298,7 @@ __global__ __launch_bounds__(kGf4Rows) void panel_select_gf4_kernel(const uint16
     __shared__ uint64_t prow[4];  // the pivot row: lo, hi, and its combination's lo, hi
     __shared__ uint32_t pinv;     // inverse of the pivot entry
     __shared__ int colpiv[kPanel];
+    __shared__ int prow_of[kPanel], pcol_of[kPanel];  // written out after the last step
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row = tid < ncand ? (in ? in[tid] : tid) : -1;
     uint64_t lo = 0, hi = 0, alo = 0, ahi = 0;
@@ -332,10 +337,8 @@ __global__ __launch_bounds__(kGf4Rows) void panel_select_gf4_kernel(const uint16
             prow[3] = ahi;
             pinv = my_inv;
             colpiv[J] = npiv;
-            st->rows[npiv] = row;
-            st->cols[npiv] = J;
-            hst->rows[npiv] = row;
-            hst->cols[npiv] = J;
+            prow_of[npiv] = row;
+            pcol_of[npiv] = J;
             used = true;
             my_t = npiv;
         }
@@ -349,6 +352,13 @@ __global__ __launch_bounds__(kGf4Rows) void panel_select_gf4_kernel(const uint16
             gf4_axpy(M1, M0, prow[3], prow[2], ahi, alo);
         }
         __syncthreads();  // prow, pinv and wcand are read before the next step writes them
+    }
+    __syncthreads();  // colpiv, prow_of and pcol_of are complete
+    if (tid < npiv) {
+        st->rows[tid] = prow_of[tid];
+        st->cols[tid] = pcol_of[tid];
+        hst->rows[tid] = prow_of[tid];
+        hst->cols[tid] = pcol_of[tid];
     }
     if (tid == 0) {
         st->rp = npiv;
