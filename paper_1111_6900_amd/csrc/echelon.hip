@@ -264,15 +264,16 @@ __global__ __launch_bounds__(ROWS * PARTS) void panel_select_kernel(const uint16
     }
 }
 
-// The final-level pivot search over F_4 (x^2 + x + 1) with every row in
-// one thread as two 64-bit planes (bit c of lo / hi: the x^0 / x^1
-// coefficient of column c), so that a step is a few word operations per
-// row instead of one table lookup per entry.  Same results as
+// The final-level pivot search over F_4 (x^2 + x + 1) in one wave: lane l
+// holds candidate rows l and l + 64, each as two 64-bit planes (bit c of lo
+// / hi: the x^0 / x^1 coefficient of column c), so that a step is two
+// ballots, a broadcast of the pivot row by lane reads and a dozen word
+// operations per row, with no barrier.  Same results as
 // panel_select_kernel<ROWS, PARTS, *, true>: the first row (in candidate
 // order) with a nonzero entry in column J becomes pivot J, column J is
 // eliminated from every other row (Gauss-Jordan), the combinations a (over
-// pivot columns) are carried along, and W = K^{-1}.  ROWS = 128 candidates,
-// one per thread.
+// pivot columns) are carried along, and W = K^{-1}.  Up to kGf4Rows = 128
+// candidates.
 constexpr int kGf4Rows = 128;
 
 // m * (h x + l) over F_4 on bit-planes, m = m1 x + m0 as all-ones masks
@@ -289,90 +290,114 @@ __device__ __attribute__((always_inline)) inline uint32_t gf4_mul(uint32_t a, ui
     const uint32_t a1 = a >> 1, a0 = a & 1, b1 = b >> 1, b0 = b & 1;
     return (((a1 & b1) ^ (a1 & b0) ^ (a0 & b1)) << 1) | ((a1 & b1) ^ (a0 & b0));
 }
-
-__global__ __launch_bounds__(kGf4Rows) void panel_select_gf4_kernel(const uint16_t* orig, int64_t r, int bc,
-                                                                    const int* in, int64_t ncand, PanelState* st,
-                                                                    PanelState* hst, void* W)
+__device__ __attribute__((always_inline)) inline uint32_t gf4_at(uint64_t hi, uint64_t lo, int c)
 {
-    __shared__ int wcand[kGf4Rows / 64];
-    __shared__ uint64_t prow[4];  // the pivot row: lo, hi, and its combination's lo, hi
-    __shared__ uint32_t pinv;     // inverse of the pivot entry
+    return uint32_t(((hi >> c) & 1) << 1 | ((lo >> c) & 1));
+}
+// x from lane `src` of the wave (src uniform).
+__device__ __attribute__((always_inline)) inline uint64_t lane_read64(uint64_t x, int src)
+{
+    const uint32_t l = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), src));
+    const uint32_t h = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), src));
+    return uint64_t(l) | (uint64_t(h) << 32);
+}
+
+// One candidate row (slot) of the F_4 search: its planes and combination.
+struct Gf4Row {
+    uint64_t lo = 0, hi = 0, alo = 0, ahi = 0;
+    int row = -1, t = -1;  // input row (relative to r), pivot index
+    uint32_t inv = 0;      // 1 / its pivot entry
+    bool used = true;
+};
+
+__global__ __launch_bounds__(64) void panel_select_gf4_kernel(const uint16_t* orig, int64_t r, int bc, const int* in,
+                                                              int64_t ncand, PanelState* st, PanelState* hst,
+                                                              void* W)
+{
     __shared__ int colpiv[kPanel];
     __shared__ int prow_of[kPanel], pcol_of[kPanel];  // written out after the last step
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row = tid < ncand ? (in ? in[tid] : tid) : -1;
-    uint64_t lo = 0, hi = 0, alo = 0, ahi = 0;
-    if (row >= 0) {
-        const uint16_t* src = orig + (r + row) * kPanel;
-        for (int c = 0; c < bc; ++c) {
-            const uint64_t x = src[c];
-            lo |= (x & 1) << c;
-            hi |= ((x >> 1) & 1) << c;
+    const int lane = threadIdx.x;
+    Gf4Row R[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int slot = lane + 64 * h;
+        R[h].row = slot < ncand ? (in ? in[slot] : slot) : -1;
+        R[h].used = R[h].row < 0;
+        if (R[h].row >= 0) {
+            // the panel copy's rows are 64 uint16 (128 bytes): 8 loads of 16 bytes
+            const uint4* src = reinterpret_cast<const uint4*>(orig + (r + R[h].row) * kPanel);
+#pragma unroll
+            for (int q = 0; q < kPanel / 8; ++q) {
+                const uint4 v = src[q];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint64_t x = (w[k >> 1] >> (16 * (k & 1))) & 3u;
+                    R[h].lo |= (x & 1) << (8 * q + k);
+                    R[h].hi |= (x >> 1) << (8 * q + k);
+                }
+            }
+            const uint64_t keep = bc >= 64 ? ~uint64_t(0) : (uint64_t(1) << bc) - 1;  // (columns past bc are zero)
+            R[h].lo &= keep;
+            R[h].hi &= keep;
         }
     }
-    if (tid < kPanel) colpiv[tid] = -1;
-    bool used = row < 0;
-    int npiv = 0, my_t = -1;
-    uint32_t my_inv = 0;
+    colpiv[lane] = -1;
+    int npiv = 0;
     for (int J = 0; J < bc; ++J) {
-        // the first candidate with a nonzero entry in column J
-        const bool ok = !used && (((lo | hi) >> J) & 1);
-        const uint64_t bal = __ballot(ok);
-        if (lane == 0) wcand[wave] = bal ? wave * 64 + __ffsll(static_cast<long long>(bal)) - 1 : INT_MAX;
-        __syncthreads();
-        int p = INT_MAX;
-#pragma unroll
-        for (int w = 0; w < kGf4Rows / 64; ++w) p = min(p, wcand[w]);
-        if (p == INT_MAX) {  // no pivot in column J (uniform)
-            __syncthreads();  // wcand is read before the next step writes it
-            continue;
-        }
-        if (tid == p) {
-            alo |= uint64_t(1) << J;  // the pivot row's own coefficient
-            const uint32_t x = uint32_t(((hi >> J) & 1) << 1 | ((lo >> J) & 1));
-            my_inv = x == 1 ? 1u : x ^ 1u;  // 1/x: 1 -> 1, x -> x + 1, x + 1 -> x
-            prow[0] = lo;
-            prow[1] = hi;
-            prow[2] = alo;
-            prow[3] = ahi;
-            pinv = my_inv;
-            colpiv[J] = npiv;
-            prow_of[npiv] = row;
+        // the first candidate (slots 0..63, then 64..127) with a nonzero entry in column J
+        const uint64_t b0 = __ballot(!R[0].used && (((R[0].lo | R[0].hi) >> J) & 1));
+        const uint64_t b1 = __ballot(!R[1].used && (((R[1].lo | R[1].hi) >> J) & 1));
+        if (!b0 && !b1) continue;  // no pivot in column J (uniform)
+        const int ph = b0 ? 0 : 1;
+        const int pl = __ffsll(static_cast<long long>(b0 ? b0 : b1)) - 1;
+        const bool mine = lane == pl;
+        // the pivot row's own coefficient, then the row to every lane
+        if (mine) (ph ? R[1] : R[0]).alo |= uint64_t(1) << J;
+        const Gf4Row& P = ph ? R[1] : R[0];
+        const uint64_t plo = lane_read64(P.lo, pl), phi = lane_read64(P.hi, pl);
+        const uint64_t palo = lane_read64(P.alo, pl), pahi = lane_read64(P.ahi, pl);
+        const uint32_t x = gf4_at(phi, plo, J);
+        const uint32_t pinv = x == 1 ? 1u : x ^ 1u;  // 1/x: 1 -> 1, x -> x + 1, x + 1 -> x
+        if (mine) {
+            Gf4Row& Q = ph ? R[1] : R[0];
+            Q.used = true;
+            Q.t = npiv;
+            Q.inv = pinv;
+            prow_of[npiv] = Q.row;
             pcol_of[npiv] = J;
-            used = true;
-            my_t = npiv;
+            colpiv[J] = npiv;
         }
         ++npiv;  // uniform
-        __syncthreads();
-        if (tid != p) {
-            const uint32_t x = uint32_t(((hi >> J) & 1) << 1 | ((lo >> J) & 1));
-            const uint32_t mlt = gf4_mul(x, pinv);  // 0 for rows with nothing to eliminate
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (mine && h == ph) continue;
+            const uint32_t mlt = gf4_mul(gf4_at(R[h].hi, R[h].lo, J), pinv);  // 0: nothing to eliminate
             const uint64_t M1 = 0 - uint64_t(mlt >> 1), M0 = 0 - uint64_t(mlt & 1);
-            gf4_axpy(M1, M0, prow[1], prow[0], hi, lo);
-            gf4_axpy(M1, M0, prow[3], prow[2], ahi, alo);
+            gf4_axpy(M1, M0, phi, plo, R[h].hi, R[h].lo);
+            gf4_axpy(M1, M0, pahi, palo, R[h].ahi, R[h].alo);
         }
-        __syncthreads();  // prow, pinv and wcand are read before the next step writes them
     }
     __syncthreads();  // colpiv, prow_of and pcol_of are complete
-    if (tid < npiv) {
-        st->rows[tid] = prow_of[tid];
-        st->cols[tid] = pcol_of[tid];
-        hst->rows[tid] = prow_of[tid];
-        hst->cols[tid] = pcol_of[tid];
+    if (lane < npiv) {
+        st->rows[lane] = prow_of[lane];
+        st->cols[lane] = pcol_of[lane];
+        hst->rows[lane] = prow_of[lane];
+        hst->cols[lane] = pcol_of[lane];
     }
-    if (tid == 0) {
+    if (lane == 0) {
         st->rp = npiv;
         hst->rp = npiv;
     }
     // W[t][s] = coefficient of pivot row s (at its column) in pivot row t, over t's pivot
-    if (my_t >= 0)
-        for (int c = 0; c < bc; ++c) {
-            const int s2 = colpiv[c];
-            if (s2 >= 0) {
-                const uint32_t a = uint32_t(((ahi >> c) & 1) << 1 | ((alo >> c) & 1));
-                st_el(W, 0, int64_t(my_t) * npiv + s2, gf4_mul(a, my_inv));
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (R[h].t >= 0)
+            for (int c = 0; c < bc; ++c) {
+                const int s2 = colpiv[c];
+                if (s2 >= 0)
+                    st_el(W, 0, int64_t(R[h].t) * npiv + s2, gf4_mul(gf4_at(R[h].ahi, R[h].alo, c), R[h].inv));
             }
-        }
 }
 
 // G[i][t] = original entry of (new) row i at pivot column t, for all rows:
@@ -828,7 +853,7 @@ int Ctx::echelon(gf2e_mat* A, int e, uint32_t f, int full, int64_t* rank, int64_
             hipLaunchKernelGGL(panel_copy_kernel, dim3(unsigned(ceil_div(m * kPanel, 256))), dim3(256), 0, s2,
                                A->data, lda, m, c0n, bcn, wide, orig);
         if (e == 2)
-            hipLaunchKernelGGL(panel_select_gf4_kernel, dim3(1), dim3(kGf4Rows), 0, s2, orig, r0, bcn,
+            hipLaunchKernelGGL(panel_select_gf4_kernel, dim3(1), dim3(64), 0, s2, orig, r0, bcn,
                                static_cast<const int*>(nullptr), std::min<int64_t>(m - r0, kGf4Rows), st, hst_dev,
                                static_cast<void*>(W));
         else if (e >= kShortProbeMinE)
