@@ -603,14 +603,15 @@ __device__ __attribute__((always_inline)) inline void stage_barrier()
     asm volatile("" ::: "memory");
 }
 
-// The 128x128 tile with both sides packed, its operands moved from HBM into
-// LDS by the direct global-to-LDS load (16 bytes per lane: two rows of one
-// k-word, lane l's pair at 16 l bytes from the wave's LDS address), four
-// LDS buffers deep: stages st + 1 .. st + 3 are in flight while stage st
-// computes, with no staging registers and no LDS store instructions.  LDS
-// holds each side as [buffer][k-word][row] 64-bit words, rows padded by 16
-// so that the two k-words a read touches fall on different halves of the
-// 64 banks (37 KiB per workgroup, four workgroups per compute unit).
+// A BM x BN tile (multiples of 128; the product kernel runs 128 x 128) with
+// both sides packed, its operands moved from HBM into LDS by the direct
+// global-to-LDS load (16 bytes per lane: two rows of one k-word, lane l's
+// pair at 16 l bytes from the wave's LDS address), four LDS buffers deep:
+// stages st + 1 .. st + 3 are in flight while stage st computes, with no
+// staging registers and no LDS store instructions.  LDS holds each side as
+// [buffer][k-word][row] 64-bit words, rows padded by 16 so that the two
+// k-words a read touches fall on different halves of the 64 banks (37 KiB
+// per 128 x 128 workgroup, four workgroups per compute unit).
 template <int BM, int BN, int WM, int WN>
 __device__ __attribute__((always_inline)) inline void fp4_tile_dma(
     const uint64_t* __restrict__ Apl, const uint64_t* __restrict__ Bpl, uint64_t* __restrict__ Ps,
